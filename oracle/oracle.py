@@ -1,0 +1,237 @@
+"""ctypes front end of the FP64 reference tracker (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+import this module.  The library it loads (``liboracle.so``) is built from
+``tpc_oracle.cpp`` by :func:`build`; it shares no code with the HIP path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+ORC_SORTED_ID, ORC_BIN_START, ORC_ROW_DIMS, ORC_UP0, ORC_DOWN0, ORC_UP1, ORC_DOWN1, ORC_STARTS, \
+    ORC_TK_ROWHIT, ORC_TK_NHITS, ORC_TK_PARAM, ORC_TK_COV, ORC_TK_XREF_ROW, ORC_TK_CHI2, \
+    ORC_TRK_TRACKLET, ORC_TRK_FIRST, ORC_TRK_CLUSTERS, ORC_SIZES = range(1, 19)
+
+
+def build(force=True):
+    """Compile liboracle.so with g++ (-O2, no FP contraction)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    src = os.path.join(HERE, "tpc_oracle.cpp")
+    tmp = LIB_PATH + ".tmp"
+    subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                           "-shared", "-Wall", "-o", tmp, src])
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Cfg(C.Structure):
+    _fields_ = [
+        ("n_rows", C.c_int32), ("row_x", C.POINTER(C.c_double)), ("row_half_y", C.POINTER(C.c_double)),
+        ("bz", C.c_double), ("sigma_y", C.c_double), ("sigma_z", C.c_double),
+        ("grid_hits_per_bin", C.c_int32),
+        ("win_a_y", C.c_double), ("win_b_y", C.c_double), ("win_a_z", C.c_double), ("win_b_z", C.c_double),
+        ("link_nsigma", C.c_double), ("s_max", C.c_double), ("seed_qpt_max", C.c_double),
+        ("c0_sinphi", C.c_double), ("c0_tanl", C.c_double), ("c0_qpt", C.c_double),
+        ("gate_nsigma", C.c_double), ("win_cap", C.c_double), ("edge_margin", C.c_double),
+        ("max_miss", C.c_int32), ("min_tracklet_hits", C.c_int32), ("min_track_hits", C.c_int32),
+        ("min_owned_frac", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        vp, u32p, dp, fp = C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_double), C.POINTER(C.c_float)
+        L.orc_run_create.restype = vp
+        L.orc_run_create.argtypes = [C.POINTER(_Cfg), C.c_uint32, u32p, dp, dp, fp, fp]
+        L.orc_run_destroy.argtypes = [vp]
+        for f in ("orc_run_grid", "orc_run_links", "orc_run_starts", "orc_run_select"):
+            getattr(L, f).argtypes = [vp]
+            getattr(L, f).restype = C.c_int
+        L.orc_run_construct.argtypes = [vp, u32p, C.c_uint64]
+        L.orc_get.restype = C.c_uint64
+        L.orc_get.argtypes = [vp, C.c_int, vp, C.c_uint64]
+        L.orc_propagate.restype = C.c_int
+        L.orc_propagate.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_propagate_cov.restype = C.c_int
+        L.orc_propagate_cov.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_kf_update.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_seed.restype = C.c_int
+        L.orc_seed.argtypes = [C.POINTER(_Cfg)] + [C.c_double] * 8 + [dp]
+        L.orc_bin.argtypes = [C.c_float] * 6 + [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_grid_dims.argtypes = [C.c_uint32, C.c_int, C.c_int64, C.c_int64, C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int)]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+class Config:
+    """Holds a config dict plus the ctypes struct (keeps the row arrays alive)."""
+
+    def __init__(self, cfg: dict):
+        self.d = dict(cfg)
+        self.row_x = np.ascontiguousarray(cfg["row_x"], np.float64)
+        self.row_half_y = np.ascontiguousarray(cfg["row_half_y"], np.float64)
+        s = _Cfg()
+        s.n_rows = len(self.row_x)
+        s.row_x = _ptr(self.row_x, C.c_double)
+        s.row_half_y = _ptr(self.row_half_y, C.c_double)
+        for name, typ in _Cfg._fields_[3:]:
+            setattr(s, name, typ(cfg[name]).value if typ is not C.c_int32 else int(cfg[name]))
+        self.s = s
+
+
+class Run:
+    """One oracle run over an event (sector-major clusters)."""
+
+    def __init__(self, cfg: dict, row_offsets, y, z, z_lo, z_hi):
+        self.cfg = Config(cfg)
+        self.R = self.cfg.s.n_rows
+        self.row_offsets = np.ascontiguousarray(row_offsets, np.uint32)
+        self.S = (len(self.row_offsets) - 1) // self.R
+        self.y = np.ascontiguousarray(y, np.float64)
+        self.z = np.ascontiguousarray(z, np.float64)
+        self.z_lo = np.ascontiguousarray(z_lo, np.float32)
+        self.z_hi = np.ascontiguousarray(z_hi, np.float32)
+        self.h = lib().orc_run_create(C.byref(self.cfg.s), self.S, _ptr(self.row_offsets, C.c_uint32),
+                                      _ptr(self.y, C.c_double), _ptr(self.z, C.c_double),
+                                      _ptr(self.z_lo, C.c_float), _ptr(self.z_hi, C.c_float))
+
+    @classmethod
+    def from_event(cls, cfg, ev, fp64=None):
+        y = ev.y if fp64 is None else fp64[0]
+        z = ev.z if fp64 is None else fp64[1]
+        return cls(cfg, ev.row_offsets, y, z, ev.sector_z_lo, ev.sector_z_hi)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_run_destroy(self.h)
+            self.h = None
+
+    def get(self, what, dtype):
+        n = lib().orc_get(self.h, what, None, 0)
+        out = np.empty(n // np.dtype(dtype).itemsize, dtype)
+        if n:
+            lib().orc_get(self.h, what, out.ctypes.data_as(C.c_void_p), n)
+        return out
+
+    def grid(self):
+        lib().orc_run_grid(self.h)
+        return self
+
+    def links(self):
+        lib().orc_run_links(self.h)
+        return self
+
+    def starts(self):
+        lib().orc_run_starts(self.h)
+        return self
+
+    def construct(self, which=None):
+        if which is None:
+            lib().orc_run_construct(self.h, None, 0)
+        else:
+            w = np.ascontiguousarray(which, np.uint32)
+            lib().orc_run_construct(self.h, _ptr(w, C.c_uint32), len(w))
+        return self
+
+    def select(self):
+        lib().orc_run_select(self.h)
+        return self
+
+    def run_all(self):
+        return self.grid().links().starts().construct().select()
+
+    # ---- results ----
+    def sizes(self):
+        return self.get(ORC_SIZES, np.uint64)
+
+    def result(self):
+        """Dict of every array the run produced."""
+        R = self.R
+        T = int(self.sizes()[1])
+        out = dict(
+            sorted_id=self.get(ORC_SORTED_ID, np.uint32), bin_start=self.get(ORC_BIN_START, np.uint32),
+            row_dims=self.get(ORC_ROW_DIMS, np.uint32), up0=self.get(ORC_UP0, np.int32),
+            down0=self.get(ORC_DOWN0, np.int32), up1=self.get(ORC_UP1, np.int32),
+            down1=self.get(ORC_DOWN1, np.int32), starts=self.get(ORC_STARTS, np.uint32),
+            tk_rowhit=self.get(ORC_TK_ROWHIT, np.int32).reshape(T, R) if T else np.zeros((0, R), np.int32),
+            tk_nhits=self.get(ORC_TK_NHITS, np.int32), tk_param=self.get(ORC_TK_PARAM, np.float64).reshape(-1, 5),
+            tk_cov=self.get(ORC_TK_COV, np.float64).reshape(-1, 15), tk_xref_row=self.get(ORC_TK_XREF_ROW, np.int32),
+            tk_chi2=self.get(ORC_TK_CHI2, np.float64), trk_tracklet=self.get(ORC_TRK_TRACKLET, np.uint32),
+            trk_first=self.get(ORC_TRK_FIRST, np.uint32), trk_clusters=self.get(ORC_TRK_CLUSTERS, np.uint32))
+        return out
+
+
+def propagate(p, x1, x2, bz, s_max=0.99):
+    p = np.ascontiguousarray(p, np.float64)
+    q = np.zeros(5)
+    F = np.zeros(25)
+    rc = lib().orc_propagate(_ptr(p, C.c_double), x1, x2, bz, s_max, _ptr(q, C.c_double), _ptr(F, C.c_double))
+    return rc, q, F.reshape(5, 5)
+
+
+def propagate_cov(p, C15, x1, x2, bz, s_max=0.99):
+    p = np.ascontiguousarray(p, np.float64)
+    c = np.ascontiguousarray(C15, np.float64)
+    q = np.zeros(5)
+    c2 = np.zeros(15)
+    rc = lib().orc_propagate_cov(_ptr(p, C.c_double), _ptr(c, C.c_double), x1, x2, bz, s_max,
+                                 _ptr(q, C.c_double), _ptr(c2, C.c_double))
+    return rc, q, c2
+
+
+def kf_update(p, C15, ym, zm, vy, vz):
+    p = np.array(p, np.float64)
+    c = np.array(C15, np.float64)
+    chi2 = C.c_double(0.0)
+    lib().orc_kf_update(_ptr(p, C.c_double), _ptr(c, C.c_double), ym, zm, vy, vz, C.byref(chi2))
+    return p, c, chi2.value
+
+
+def seed(cfg: dict, x0, y0, z0, xm, ym, xl, yl, zl):
+    c = Config(cfg)
+    p = np.zeros(5)
+    rc = lib().orc_seed(C.byref(c.s), x0, y0, z0, xm, ym, xl, yl, zl, _ptr(p, C.c_double))
+    return rc, p
+
+
+def bin_of(y, z, y_lo, inv_wy, z_lo, inv_wz, ny, nz):
+    iy, iz = C.c_int(), C.c_int()
+    lib().orc_bin(y, z, y_lo, inv_wy, z_lo, inv_wz, ny, nz, C.byref(iy), C.byref(iz))
+    return iy.value, iz.value
+
+
+def grid_dims(n, k, ly, lz):
+    ny, nz = C.c_int(), C.c_int()
+    lib().orc_grid_dims(n, k, ly, lz, C.byref(ny), C.byref(nz))
+    return ny.value, nz.value
+
+
+def unpack_cov(c15):
+    """Packed lower triangle (00,10,11,20,...) -> symmetric 5x5."""
+    M = np.zeros((5, 5))
+    k = 0
+    for i in range(5):
+        for j in range(i + 1):
+            M[i, j] = M[j, i] = c15[k]
+            k += 1
+    return M
