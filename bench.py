@@ -1,0 +1,173 @@
+"""Benchmark: TPC clusters/s tracked on one MI355X (plain path, one time frame per step).
+
+One step = steps C1..C7 over the whole workload: enqueue the time frame
+(device-resident clusters), wait for it, copy the compact track output to
+host memory, release.  The default workload is one central heavy-ion-like
+event in all 36 sectors (seeded synthetic data, about 1.28M clusters).
+
+Prints one JSON line with the headline value, per-step latency percentiles,
+per-pass HIP-event times, the roofline entry of the dominant kernel and the
+FP64 oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes (see the per-pass table in the design notes)
+K5_BYTES_PER_STEP = 30.0        # bin-start pair, ~2 candidate (y, z) pairs, row->hit entry
+K5_BYTES_PER_TRACKLET = 700.0   # chain walk, seed reads, state/covariance/row column writes
+K1_BYTES_PER_CLUSTER = 22.0     # read y, z; write sorted (y, z), id, ~2 B of bin starts
+K2_BYTES_PER_CLUSTER = 18.0     # read own (y, z) + each adjacent row once + bin starts; write up0/down0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2502_09138_amd import synth
+    if name == "central_event":
+        return synth.central_event(seed=2), dict(workload="central_event", seed=2, n_primaries=8000,
+                                                 secondary_frac=0.1)
+    if name == "single_sector":
+        return synth.single_sector(seed=1), dict(workload="single_sector", seed=1, n_tracks=200)
+    if name == "time_frame":
+        return synth.time_frame(seed=3), dict(workload="time_frame", seed=3, n_orbits=32, rate_khz=50)
+    if name == "uneven_chunks":
+        return synth.uneven_chunks(), dict(workload="uneven_chunks", seed0=1000, n_chunks=512)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(ev, budget_s):
+    """FP64 oracle, single thread, on whole sectors until ~budget_s of CPU work."""
+    from oracle import oracle
+    from paper_2502_09138_amd.config import default_config
+    cfg = default_config().as_dict()
+    R = 152
+    done_clusters, t_total, sectors = 0, 0.0, []
+    for s in range(ev.n_sectors):
+        sub = ev.sector_slice([s])
+        t0 = time.perf_counter()
+        oracle.Run.from_event(cfg, sub).run_all()
+        t_total += time.perf_counter() - t0
+        done_clusters += sub.n_clusters
+        sectors.append(s)
+        if t_total >= budget_s:
+            break
+    return dict(value=done_clusters / t_total, unit="clusters/s", cores=1, kind="oracle",
+                sample=f"sectors 0..{sectors[-1]} of the workload ({done_clusters} clusters), full C1-C7, "
+                       f"one thread, {t_total:.1f} s", seconds=t_total)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="central_event")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sectors and time frames "
+              "shard across GPUs with no exchange, so the per-GPU figure is the one reported)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_09138_amd.config import default_config
+    from paper_2502_09138_amd.tracker import Tracker
+
+    log(f"bench: generating {args.workload}")
+    ev, wl = make_workload(args.workload)
+    N = ev.n_clusters
+    log(f"bench: {N} clusters in {ev.n_sectors} sectors")
+    dev = torch.device("cuda", 0)
+    y = torch.from_numpy(ev.y).to(dev)
+    z = torch.from_numpy(ev.z).to(dev)
+    torch.cuda.synchronize()
+    tr = Tracker(default_config(), max_clusters=N, max_sectors=ev.n_sectors)
+    tr.set_timing(True)
+
+    def step():
+        rid = tr.submit(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+        out = tr.get(rid)
+        counts = tr.get_counts(rid)
+        passes = tr.pass_times()
+        tr.release(rid)
+        return out, counts, passes
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, pass_acc = [], {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        out, counts, passes = step()
+        lat.append(time.perf_counter() - s0)
+        for k, v in passes.items():
+            pass_acc.setdefault(k, []).append(v)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"bench: {args.steps} steps in {elapsed:.3f} s; tracks {out.n_tracks}, tracklets {counts['n_tracklets']}")
+
+    value = N * args.steps / elapsed
+    pass_ms = {k: float(np.mean(v)) for k, v in pass_acc.items()}
+    dominant = max(pass_ms, key=pass_ms.get)
+    k5_bytes = K5_BYTES_PER_STEP * counts["n_steps"] + K5_BYTES_PER_TRACKLET * counts["n_tracklets"]
+    k5_gbs = k5_bytes / (pass_ms["tracklets"] * 1e-3) / 1e9
+    k1_gbs = K1_BYTES_PER_CLUSTER * N / (pass_ms["grid"] * 1e-3) / 1e9
+    k2_gbs = K2_BYTES_PER_CLUSTER * N / (pass_ms["neighbours"] * 1e-3) / 1e9
+    roof = {
+        "tracklets": dict(kernel="k_tracklets (K5, C5)", bound="hbm", achieved=round(k5_gbs, 2), peak=HBM_PEAK_GBS,
+                          unit="GB/s", frac=round(k5_gbs / HBM_PEAK_GBS, 5), traffic=None,
+                          note="latency-bound dependent gathers; bytes = 30 B/row step + 700 B/tracklet"),
+        "grid": dict(kernel="k_grid_lds (K1, C1)", bound="hbm", achieved=round(k1_gbs, 2), peak=HBM_PEAK_GBS,
+                     unit="GB/s", frac=round(k1_gbs / HBM_PEAK_GBS, 5), traffic=None),
+        "neighbours": dict(kernel="k_links (K2, C2)", bound="hbm", achieved=round(k2_gbs, 2), peak=HBM_PEAK_GBS,
+                           unit="GB/s", frac=round(k2_gbs / HBM_PEAK_GBS, 5), traffic=None),
+    }
+    rec = {
+        "metric": "TPC clusters/s tracked at 1 GPU (plain path) + p50/p99 time-frame latency",
+        "value": round(value, 1),
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": dict(wl, n_clusters=N, n_sectors=ev.n_sectors, n_rows=152, tracklets=counts["n_tracklets"],
+                       tracks=counts["n_tracks"]),
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 4),
+                       "p99": round(1e3 * float(np.percentile(lat, 99)), 4)},
+        "passes_ms": {k: round(v, 4) for k, v in pass_ms.items()},
+        "dominant_pass": dominant,
+        "roofline": roof.get(dominant, roof["tracklets"]),
+        "roofline_passes": roof,
+    }
+    tr.close()
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on the host")
+        cb = cpu_baseline(ev, args.cpu_budget)
+        rec["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    else:
+        rec["cpu_baseline"] = None
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,253 @@
+/*
+ * tpc_tracker.h -- C ABI of the MI355X TPC sector track finder.
+ *
+ * What it computes.  The paper (arXiv:2502.09138, Introduction and Tables 1-3)
+ * identifies TPC processing, dominated by track finding on clusters, as the
+ * step that takes essentially all of ALICE's synchronous reconstruction time
+ * and the GPU-offloaded part of the asynchronous one; it does not spell the
+ * algorithm out.  This library implements per-sector track finding on TPC
+ * clusters as a cellular-automaton neighbour search over pad rows followed
+ * by Kalman-filter tracklet construction along helices, defined here step by
+ * step (C1..C7).  Every number below is an input or a stated rule; nothing is
+ * taken from any other implementation.
+ *
+ * Notation: S sectors, R pad rows (row r at radius X_r, sector half-width Y_r),
+ * N clusters; (y, z) are sector-local coordinates in cm (z may be a drift
+ * coordinate).  Clusters arrive sector-major, row-major: the clusters of
+ * sector s, row r are [row_offsets[s*R+r], row_offsets[s*R+r+1]); a cluster's
+ * index in the input arrays is its input id.  "Sorted position" p is the index
+ * into the per-row grid order of C1 (rows keep their input ranges).
+ *
+ * C1  Grid (per sector s, row r, N_r hits).  Integer dims:
+ *       Ly = ceil(20*Y_r) [mm], Lz = ceil(10*((double)z_hi_s - (double)z_lo_s)) [mm],
+ *       B = max(1, N_r / K), nY = clamp(isqrt(B*Ly / Lz), 1, B), nZ = max(1, B / nY)
+ *     (integer divisions, K = grid_hits_per_bin).  Bin of a hit, float32
+ *     round-to-nearest, one rounding per operation, no contraction:
+ *       u = (y - y_lo) * ((float)nY * inv_wy);  u = 0 if !(u >= 0);
+ *       u = nY-1 if u > nY-1;  iy = (int)u     (same for z with z_lo, inv_wz, nZ)
+ *     with y_lo = (float)(-Y_r), inv_wy = (float)(1/(2*Y_r)),
+ *     inv_wz = (float)(1/((double)z_hi - (double)z_lo)); bin = iz*nY + iy.
+ *     Sorted order of a row: ascending (bin, input id) -- a stable counting
+ *     sort.  bin_start of row (s,r) lives at offset row_offsets[s*R+r] + 2*(s*R+r),
+ *     nBins+1 entries holding sorted positions.
+ * C2  Neighbour finder (rows 1..R-2).  du = X_{r+1}-X_r, dd = X_r-X_{r-1},
+ *     t = (float)(dd/(dd+du)), W_y(d) = (float)(a_y*d + b_y), W_z likewise,
+ *     Dmax = (float)((n^2*sigma_y^2) * ((1 + t^2) + (1-t)^2)) (double, then
+ *     rounded), rho = (float)((sigma_y/sigma_z)^2).  For hit h: U = hits u in
+ *     row r+1 with |y_u-y_h| <= W_y(du) and |z_u-z_h| <= W_z(du); D likewise in
+ *     row r-1 with dd.  For (d,u) in D x U, in float32 as written:
+ *       yp = y_d + t*(y_u-y_d); zp = z_d + t*(z_u-z_d);
+ *       ey = y_h-yp; ez = z_h-zp; dev = ey*ey + rho*(ez*ez)
+ *     Keep dev <= Dmax; choose the smallest (dev, pos_u, pos_d).  up0/down0 =
+ *     sorted positions or -1.  Rows 0 and R-1 get no links.
+ * C3  Cleaner: up1[h] = up0[h] if down0[up0[h]] == h else -1; down1[h] =
+ *     down0[h] if up0[down0[h]] == h else -1 (evaluated on the C2 snapshot).
+ * C4  Starts: down1[h] == -1 and up1[h] >= 0 and up1[up1[h]] >= 0; listed in
+ *     ascending sorted position (= sector, row, grid order).  The start index
+ *     in this list identifies the tracklet; startPos = its sorted position.
+ * C5  Tracklet constructor (one per start; state p = (y, z, sin phi, tan
+ *     lambda, q/pT) at x; kappa = -c_B*Bz*q/pT, c_B = 0.00299792458):
+ *     Propagation x1 -> x2: fail if |s1| >= s_max; s2 = s1 + kappa*dx; fail if
+ *       |s2| >= s_max; y2 = y1 + dx*(s1+s2)/(c1+c2) with c = sqrt(1-s^2);
+ *       chord L = sqrt(dx^2+dy^2); u = kappa*L/2 (fail if |u| >= 1);
+ *       ds = sign(dx)*L*asin(u)/u; z2 = z1 + tanl*ds.  Covariance C <- F C F^T
+ *       with F the exact derivative of this map; no process noise.
+ *     Update with (y_m, z_m), V = diag(sigma_y^2, sigma_z^2): standard gain,
+ *       chi2 += r^T S^-1 r.
+ *     Seed: chain h0..h_{n-1} along up1; points (X, y) of h0, h_m (m = (n-1)/2),
+ *       h_{n-1}; kappa = 2(a x b)/(|a||b||c|) (a = Pm-P0, b = Pl-Pm, c = Pl-P0);
+ *       u = kappa|c|/2 (fail if |u| >= 1); phi0 = atan2(c_y, c_x) - asin(u);
+ *       tanl = (z_l - z_0)/(|c| asin(u)/u); q/pT = kappa/(-c_B*Bz) (0 if Bz = 0)
+ *       clamped to +-seed_qpt_max; fail unless cos(phi0) > 0 and
+ *       |sin phi0| < s_max.  p = (y0, z0, sin phi0, tanl, q/pT) at X_{r0},
+ *       C = C0 = diag(sigma_y^2, sigma_z^2, c0_sinphi, c0_tanl, c0_qpt).
+ *     Chain fit: propagate row by row and update with h1..h_{n-1} (no gate).
+ *     Upward: for rows above the chain: propagate (stop on failure); stop if
+ *       |y| > Y_r + edge_margin; search; update on a hit, else count a miss and
+ *       stop after max_miss+1 consecutive misses.  Search in row r: window
+ *       w = min(g*sqrt(C_yy+sigma_y^2), cap) in y (same in z); candidate
+ *       minimising dy^2/(C_yy+sigma_y^2) + dz^2/(C_zz+sigma_z^2), ties by
+ *       smaller sorted position.
+ *     Downward refit: from the outermost hit row r_out with p from the
+ *       upward pass, (y, z) set to that hit's coordinates and C = C0; for rows
+ *       r_out-1 .. 0: propagate (stop on failure); below the start row r0
+ *       stop if |y| > Y_r + edge_margin; use the row's hit from the upward
+ *       pass without a gate, else search; count misses only below r0.
+ *     Result: hits of the downward pass; p, C at x_ref = X of the innermost
+ *       hit; chi2 of the downward pass; ndf = 2*nHits - 5.  Valid if
+ *       nHits >= min_tracklet_hits.
+ * C6  Selector: key = (nHits << 32) | (0xFFFFFFFF - startPos).  W[hit] = max
+ *     key over valid tracklets holding the hit.  Owned = hits with W == key.
+ *     Emit the tracklet as a track if owned >= min_track_hits and (float)owned
+ *     >= (float)min_owned_frac * (float)nHits (float32).
+ * C7  Output: tracks in ascending startPos (hence by sector); cluster lists are
+ *     input ids of the owned hits in ascending row; parameters are the C5
+ *     result at x_ref.
+ *
+ * Floating point: C1, C2 and the C6 fraction test are exact float32
+ * definitions (bit-identical results expected).  C5 runs in float32 on the
+ * GPU; its results agree with an FP64 evaluation of the same steps within
+ * rounding, and a search decision may differ only when two candidates (or a
+ * candidate and a window edge) are within rounding of each other.
+ *
+ * Threading: a tracker is used by one host thread at a time.  One request is
+ * in flight per tracker: tpc_track_timeframe returns TPC_E_BUSY until the
+ * previous request has been released.
+ */
+#ifndef TPC_TRACKER_H
+#define TPC_TRACKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPC_ABI_VERSION 1u
+#define TPC_MAX_ROWS 255
+#define TPC_MAX_ROW_HITS 65535u       /* clusters per (sector, row) */
+#define TPC_MAX_COORD 16384.0f        /* |y|, |z| bound (cm) for exact grid searches */
+
+typedef int32_t tpc_status;
+enum {
+  TPC_OK = 0,
+  TPC_E_INVAL = -1,      /* bad argument or configuration; nothing was enqueued */
+  TPC_E_NOMEM = -2,      /* allocation failed */
+  TPC_E_DEVICE = -3,     /* HIP runtime error */
+  TPC_E_CAPACITY = -4,   /* a capacity was exceeded (see error_flags); results discarded */
+  TPC_E_NOTREADY = -5,   /* non-blocking get on a request still running */
+  TPC_E_INPUT = -6,      /* non-finite or out-of-range cluster coordinate */
+  TPC_E_BUSY = -7        /* previous request not yet released */
+};
+
+/* device-side error flags reported in tpc_tracks.error_flags */
+enum {
+  TPC_ERR_NONFINITE = 1u,          /* a y or z is NaN/Inf or |.| > TPC_MAX_COORD */
+  TPC_ERR_TRACKLET_OVERFLOW = 2u,  /* more starts than max_tracklets */
+  TPC_ERR_TRACK_OVERFLOW = 4u,     /* more tracks than max_tracks */
+  TPC_ERR_CLUSTER_OVERFLOW = 8u    /* more track clusters than max_track_clusters */
+};
+
+typedef struct tpc_tracker tpc_tracker;
+
+typedef struct {
+  uint32_t abi_version;            /* TPC_ABI_VERSION */
+  int32_t n_rows;                  /* R, 3..TPC_MAX_ROWS */
+  const double* row_x;             /* [n_rows] pad-row radius X_r (cm), strictly increasing; copied at create */
+  const double* row_half_y;        /* [n_rows] sector half-width Y_r (cm), > 0; copied at create */
+  double bz_tesla;                 /* solenoid field */
+  double sigma_y, sigma_z;         /* cluster resolution (cm), > 0 */
+  /* cuts (C1..C6) */
+  int32_t grid_hits_per_bin;       /* K >= 1 */
+  double win_a_y, win_b_y, win_a_z, win_b_z;   /* neighbour windows W(d) = a*d + b (cm) */
+  double link_nsigma;              /* n in Dmax */
+  double s_max;                    /* |sin phi| limit, (0, 1) */
+  double seed_qpt_max;             /* |q/pT| clamp of the seed (1/GeV) */
+  double c0_sinphi, c0_tanl, c0_qpt;           /* initial variances */
+  double gate_nsigma, win_cap, edge_margin;    /* search gate g, window cap (cm), edge margin (cm) */
+  int32_t max_miss, min_tracklet_hits, min_track_hits;
+  double min_owned_frac;
+  /* capacities (device workspace is sized from these) */
+  uint32_t max_sectors;
+  uint64_t max_clusters;           /* < 2^31 */
+  uint64_t max_tracklets;          /* 0 = max_clusters / 4 */
+  uint64_t max_tracks;             /* 0 = max_tracklets */
+  uint64_t max_track_clusters;     /* 0 = max_clusters */
+  /* device and memory */
+  int32_t device;                  /* HIP device ordinal */
+  void* stream;                    /* hipStream_t to enqueue on; NULL = a stream owned by the tracker */
+  void* workspace;                 /* device memory >= tpc_workspace_bytes(cfg), 256-byte aligned, owned by
+                                      the caller and kept alive until destroy; NULL = tracker allocates */
+  uint64_t workspace_bytes;
+} tpc_tracker_config;
+
+/* Fills every field with the library defaults (geometry pointers NULL). */
+void tpc_default_config(tpc_tracker_config* cfg);
+
+/* Device bytes the tracker needs for cfg (0 if cfg is invalid).  Host only. */
+uint64_t tpc_workspace_bytes(const tpc_tracker_config* cfg);
+
+/* Validates cfg (TPC_E_INVAL before any device call), then selects the
+ * device, uploads the constant tables and carves the workspace. */
+tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out);
+void tpc_tracker_destroy(tpc_tracker* t);
+
+enum { TPC_IN_DEVICE = 0u, TPC_IN_HOST = 1u };
+
+typedef struct {
+  uint32_t n_sectors;              /* 1..max_sectors */
+  uint32_t n_rows;                 /* must equal the config's n_rows */
+  const uint32_t* row_offsets;     /* HOST [n_sectors*n_rows+1], starts at 0, non-decreasing, ends at n_clusters */
+  const float* y;                  /* [n_clusters] sector-local y (cm) */
+  const float* z;                  /* [n_clusters] z or drift coordinate (cm) */
+  const uint16_t* charge;          /* [n_clusters] or NULL; carried, not read by tracking */
+  uint64_t n_clusters;             /* <= max_clusters */
+  const float* sector_z_lo;        /* HOST [n_sectors] grid z range per sector; z_hi > z_lo */
+  const float* sector_z_hi;
+  uint32_t flags;                  /* TPC_IN_DEVICE: y/z are device pointers, borrowed until the request
+                                      completes; TPC_IN_HOST: host arrays, copied before return */
+} tpc_timeframe;
+
+/* Enqueues C1..C7 for one time frame on the tracker's stream and returns at
+ * once.  Errors in the host-side validation return TPC_E_INVAL and enqueue
+ * nothing. */
+tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* tf, uint64_t* request_id);
+
+typedef struct {
+  uint32_t n_tracks;
+  uint64_t n_track_clusters;
+  const uint32_t* track_sector;    /* [n_tracks] */
+  const uint32_t* track_start;     /* [n_tracks] startPos (sorted position of the start hit) */
+  const uint32_t* track_first;     /* [n_tracks+1] offsets into cluster_ids */
+  const uint32_t* cluster_ids;     /* [n_track_clusters] input ids, ascending row within a track */
+  const float* x_ref;              /* [n_tracks] cm */
+  const float* param;              /* [n_tracks*5] y, z, sin phi, tan lambda, q/pT at x_ref */
+  const float* cov;                /* [n_tracks*15] lower triangle row-major: 00,10,11,20,21,22,... */
+  const float* chi2;               /* [n_tracks] */
+  const int32_t* ndf;              /* [n_tracks] */
+  uint32_t error_flags;            /* TPC_ERR_* */
+  uint32_t n_tracklets;            /* number of starts (C4) */
+  uint64_t n_steps;                /* row steps taken by the C5 lanes (work measure) */
+} tpc_tracks;
+
+/* Waits for (blocking != 0) or polls the request and fills *out with views of
+ * tracker-owned host memory, valid until tpc_release or destroy.  Returns
+ * TPC_E_NOTREADY when polling a running request, TPC_E_INPUT/TPC_E_CAPACITY
+ * when the device reported an error (out->error_flags set, no tracks). */
+tpc_status tpc_get_tracks(tpc_tracker* t, uint64_t request_id, int32_t blocking, tpc_tracks* out);
+
+/* Waits for the request and frees its slot. */
+tpc_status tpc_release(tpc_tracker* t, uint64_t request_id);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* tpc_last_error(void);
+
+/* ---- introspection (tests, profiling) ---- */
+enum {
+  TPC_DBG_SORTED_ID = 1,   /* u32 [N] */
+  TPC_DBG_SORTED_YZ,       /* f32 [2N] (y, z) pairs */
+  TPC_DBG_BIN_START,       /* u32 [N + 2*S*R] (only nBins+1 entries per row defined) */
+  TPC_DBG_ROW_DIMS,        /* u32 [S*R] nY | nZ << 16 */
+  TPC_DBG_UP0, TPC_DBG_DOWN0, TPC_DBG_UP1, TPC_DBG_DOWN1,   /* i32 [N] */
+  TPC_DBG_STARTS,          /* u32 [T] */
+  TPC_DBG_TK_ROWHIT,       /* i32 [R*max_tracklets] row-major; only rows [xref_row, out_row] defined */
+  TPC_DBG_TK_INFO,         /* i32 [4*T]: nHits (<0: seed/propagation failure), xref_row, out_row, start row */
+  TPC_DBG_TK_PARAM,        /* f32 [5*T] parameter-major: param k of tracklet i at [k*max_tracklets + i] */
+  TPC_DBG_TK_COV,          /* f32 [15*max_tracklets] same layout */
+  TPC_DBG_TK_CHI2          /* f32 [T] */
+};
+/* Copies an intermediate of the last completed request to host memory;
+ * *bytes receives the full size.  Waits for the request. */
+tpc_status tpc_debug_copy(tpc_tracker* t, int32_t what, void* host_dst, uint64_t cap_bytes, uint64_t* bytes);
+
+/* Per-pass timing with HIP events on the tracker's stream. */
+#define TPC_N_PASSES 6     /* K1 grid, K2 neighbours, K3/K4 clean+starts, K5 tracklets, K6 select, output */
+tpc_status tpc_set_timing(tpc_tracker* t, int32_t enable);
+/* Milliseconds of each pass of the last completed request (needs timing on). */
+tpc_status tpc_get_pass_times(tpc_tracker* t, float* ms, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPC_TRACKER_H */

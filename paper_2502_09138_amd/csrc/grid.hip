@@ -1,0 +1,108 @@
+// K1: per-(sector,row) grid -- step C1 of the tracker definition.
+//
+// One workgroup per row.  Bins come from the exact float32 rule; the order in
+// a row is a stable counting sort by (bin, input id):
+//   1. bin every hit, LDS-atomic histogram (the returned slot is arbitrary),
+//   2. exclusive scan of the histogram -> bin starts,
+//   3. scatter local ids into their bins at the arbitrary slot,
+//   4. each position ranks its id among the (few) ids of its own bin, which
+//      restores input order inside the bin without a global sort.
+// Coordinates are checked for NaN/Inf and |.| > TPC_MAX_COORD on the way.
+// The ownership array W of step C6 is cleared here for the row's positions.
+#include "device_common.h"
+
+namespace tpc {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr uint32_t kLdsRowCap = 4096;        // rows up to this many hits run from LDS
+constexpr float kMaxCoord = 16384.0f;
+
+struct RowArrays {   // cnt[nb+1], key[n], slot[n], tmp[n]
+  uint32_t* cnt;
+  uint32_t* key;
+  uint32_t* slot;
+  uint32_t* tmp;
+};
+
+__device__ void grid_row(const DevPtrs& d, uint32_t sr, const RowArrays& A, uint32_t* wsum) {
+  const int grid_k = d.grid_k;
+  const uint32_t R = d.R;
+  const uint32_t s = sr / R, row = sr % R;
+  const uint32_t a = d.row_off[sr];
+  const uint32_t n = d.row_off[sr + 1] - a;
+  const RowConst rc = d.rows[row];
+  const SectorConst sc = d.secs[s];
+  int ny, nz;
+  grid_dims(n, grid_k, rc.ly, sc.lz, ny, nz);
+  const uint32_t nb = (uint32_t)(ny * nz);
+  if (threadIdx.x == 0) d.row_dims[sr] = (uint32_t)ny | ((uint32_t)nz << 16);
+  for (uint32_t b = threadIdx.x; b <= nb; b += blockDim.x) A.cnt[b] = 0;
+  __syncthreads();
+  bool bad = false;
+  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const float yv = d.y[a + j], zv = d.z[a + j];
+    bad |= !(fabsf(yv) <= kMaxCoord) || !(fabsf(zv) <= kMaxCoord);
+    const int iy = bin1(yv, rc.y_lo, rc.inv_wy, ny);
+    const int iz = bin1(zv, sc.z_lo, sc.inv_wz, nz);
+    const uint32_t b = (uint32_t)(iz * ny + iy);
+    A.key[j] = b;
+    A.slot[j] = atomicAdd(&A.cnt[b], 1u);
+  }
+  if (__any(bad) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&d.hdr->error_flags, 1u);
+  __syncthreads();
+  block_scan_array(A.cnt, nb, wsum);
+  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) A.tmp[A.cnt[A.key[j]] + A.slot[j]] = j;
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < n; p += blockDim.x) {
+    const uint32_t j = A.tmp[p];
+    const uint32_t b = A.key[j];
+    const uint32_t b0 = A.cnt[b], b1 = A.cnt[b + 1];
+    uint32_t rank = 0;
+    for (uint32_t q = b0; q < b1; ++q) rank += A.tmp[q] < j;
+    const uint32_t out = a + b0 + rank;
+    d.sid[out] = a + j;
+    d.syz[out] = make_float2(d.y[a + j], d.z[a + j]);
+    d.W[a + p] = 0ull;
+  }
+  __syncthreads();
+  // row-local bin starts -> global sorted positions (in place when cnt is the bin_start row itself)
+  const uint32_t base = bin_base(d, sr);
+  for (uint32_t b = threadIdx.x; b <= nb; b += blockDim.x) d.bin_start[base + b] = a + A.cnt[b];
+}
+
+__global__ void __launch_bounds__(kThreads) k_grid_lds(DevPtrs d, uint32_t cap) {
+  extern __shared__ uint32_t lds[];
+  __shared__ uint32_t wsum[kThreads / kWave];
+  const uint32_t sr = blockIdx.x;
+  const uint32_t n = d.row_off[sr + 1] - d.row_off[sr];
+  if (n > cap) return;            // handled by k_grid_global
+  RowArrays A{lds, lds + cap + 2, lds + 2 * cap + 2, lds + 3 * cap + 2};
+  grid_row(d, sr, A, wsum);
+}
+
+// Rows larger than the LDS capacity: the same steps with the arrays in global
+// memory.  The counts use the row's own bin_start slots (n + 2 >= nBins + 1);
+// key/slot/order use the row's range of the C2/C3 link arrays, which are
+// written only later.
+__global__ void __launch_bounds__(kThreads) k_grid_global(DevPtrs d, uint32_t cap) {
+  __shared__ uint32_t wsum[kThreads / kWave];
+  const uint32_t sr = blockIdx.x;
+  const uint32_t a = d.row_off[sr];
+  const uint32_t n = d.row_off[sr + 1] - a;
+  if (n <= cap) return;
+  RowArrays A{d.bin_start + bin_base(d, sr), (uint32_t*)d.up0 + a, (uint32_t*)d.down0 + a, (uint32_t*)d.up1 + a};
+  grid_row(d, sr, A, wsum);
+}
+
+}  // namespace
+
+void launch_grid(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s) {
+  if (d.SR == 0) return;
+  const uint32_t cap = max_row_hits < kLdsRowCap ? max_row_hits : kLdsRowCap;
+  const size_t lds = (size_t)(4 * cap + 2) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_grid_lds, dim3(d.SR), dim3(kThreads), lds, s, d, cap);
+  if (max_row_hits > kLdsRowCap) hipLaunchKernelGGL(k_grid_global, dim3(d.SR), dim3(kThreads), 0, s, d, cap);
+}
+
+}  // namespace tpc

@@ -1,0 +1,121 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpc {
+
+constexpr int kMaxRows = 255;
+constexpr float kWinPad = 0.01f;    // cm added to a search window before binning (covers rounding)
+constexpr int kPasses = 6;
+
+// Per pad row: float32 constants used by C1, C2 and C5 (computed in double on the host, rounded once).
+struct RowConst {
+  float x, half_y, y_lo, inv_wy;
+  float t, wy_up, wz_up, wy_dn;
+  float wz_dn, dmax;
+  int32_t ly;          // ceil(20 * Y_r), mm
+  int32_t pad;
+};
+
+// Per sector of the current request.
+struct SectorConst {
+  float z_lo, inv_wz;
+  int32_t lz;          // mm
+  int32_t pad;
+};
+
+// Scalar constants of C5/C6 in float32.
+struct KfConst {
+  float bk;            // -c_B * Bz
+  float s_max, qpt_max;
+  float vy, vz;        // sigma^2
+  float c0_sinphi, c0_tanl, c0_qpt;
+  float gate, cap, margin;
+  float rho;
+  float min_owned_frac;
+  int32_t max_miss, min_tracklet_hits, min_track_hits;
+  int32_t grid_k;
+  int32_t n_rows;
+};
+
+// Device result header (copied to pinned host memory at the end of a request).
+struct ResultHeader {
+  uint32_t n_starts;       // C4 count (may exceed capacity; see flags)
+  uint32_t error_flags;
+  uint32_t n_tracks;
+  uint32_t pad0;
+  uint64_t n_track_clusters;
+  uint64_t n_steps;        // row steps taken by all tracklet lanes (C5 work measure)
+};
+
+// All device pointers of one request.
+struct DevPtrs {
+  // inputs
+  const uint32_t* row_off;   // [SR+1]
+  const float* y;
+  const float* z;
+  const RowConst* rows;      // [R]
+  const SectorConst* secs;   // [S]
+  // C1
+  uint32_t* row_dims;        // [SR]
+  uint32_t* bin_start;       // [N + 2SR]
+  float2* syz;               // [N]
+  uint32_t* sid;             // [N]
+  // C2/C3/C4
+  int32_t* up0;
+  int32_t* down0;
+  int32_t* up1;
+  int32_t* down1;
+  uint8_t* sflag;            // [N] start flag
+  uint32_t* row_nstart;      // [SR]
+  uint32_t* row_start_off;   // [SR+1] exclusive scan
+  uint32_t* start_pos;       // [Tcap]
+  uint32_t* start_sr;        // [Tcap]
+  // C5
+  int32_t* tk_rowhit;        // [R * Tcap]
+  int32_t* tk_info;          // [4 * Tcap]: nHits, r_in, r_out, r0
+  float* tk_param;           // [5 * Tcap]
+  float* tk_cov;             // [15 * Tcap]
+  float* tk_chi2;            // [Tcap]
+  // C6
+  unsigned long long* W;     // [N]
+  unsigned long long* tk_pack;   // [Tcap] (owned << 32) | accepted
+  unsigned long long* tk_scan;   // [Tcap + 1] exclusive scan of tk_pack
+  // outputs
+  uint32_t* out_sector;
+  uint32_t* out_start;
+  uint32_t* out_first;       // [max_tracks + 1]
+  uint32_t* out_clusters;
+  float* out_xref;
+  float* out_param;          // [5 * max_tracks] track-major
+  float* out_cov;            // [15 * max_tracks]
+  float* out_chi2;
+  int32_t* out_ndf;
+  // scratch for scans
+  unsigned long long* scan_blocks;   // [kScanMaxBlocks]
+  ResultHeader* hdr;
+  // sizes
+  int32_t grid_k;
+  float rho;                 // (sigma_y / sigma_z)^2, float32
+  uint32_t S, R, SR, N;
+  uint32_t tcap;
+  uint32_t max_tracks;
+  uint64_t max_track_clusters;
+};
+
+constexpr int kScanBlock = 1024;                   // elements per scan block (256 threads x 4)
+constexpr int kScanMaxBlocks = 8192;               // supports scans of up to 8M elements
+
+// ---- launch wrappers (each in its own .hip file) ----
+void launch_grid(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
+void launch_links(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
+void launch_clean_starts(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
+void launch_tracklets(const DevPtrs& d, const KfConst& k, hipStream_t s);
+void launch_select(const DevPtrs& d, const KfConst& k, hipStream_t s);
+// exclusive scans; n read from *n_dev when n_dev != nullptr (then n_max bounds the grid)
+void launch_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, unsigned long long* blocks, hipStream_t s);
+void launch_scan_u64(const unsigned long long* in, unsigned long long* out, const uint32_t* n_dev, uint32_t n_max,
+                     unsigned long long* blocks, hipStream_t s);
+
+}  // namespace tpc

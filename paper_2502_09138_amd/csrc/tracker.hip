@@ -1,0 +1,593 @@
+// Host runtime of the C ABI declared in include/tpc_tracker.h.
+//
+// create:  validate the configuration, derive the float32 constant tables
+//          (double arithmetic, one rounding), carve one device workspace,
+//          allocate pinned staging/output buffers.
+// track:   validate the time frame on the host, stage row offsets and sector
+//          constants, enqueue K1..K6 on one stream with no host sync, copy the
+//          result header to pinned memory and record a completion event.
+// get:     wait for the event, copy the compact outputs to pinned memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tpc_tracker.h"
+#include "tpc_internal.h"
+
+using namespace tpc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tpc_status fail(tpc_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(TPC_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double kCB = 0.00299792458;
+constexpr uint64_t kAlign = 256;
+
+struct Layout {   // byte offsets of every workspace buffer
+  uint64_t row_off, rows, secs, row_dims, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
+      row_start_off, start_pos, start_sr, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, W, tk_pack, tk_scan,
+      out_sector, out_start, out_first, out_clusters, out_xref, out_param, out_cov, out_chi2, out_ndf, scan_blocks,
+      hdr, in_y, in_z, total;
+};
+
+struct Caps {
+  uint64_t N, SRmax, T, MT, MC;
+  uint32_t R, Smax;
+};
+
+Caps caps_of(const tpc_tracker_config& c) {
+  Caps k;
+  k.R = (uint32_t)c.n_rows;
+  k.Smax = c.max_sectors;
+  k.N = c.max_clusters;
+  k.SRmax = (uint64_t)c.max_sectors * k.R;
+  k.T = c.max_tracklets ? c.max_tracklets : std::max<uint64_t>(1, c.max_clusters / 4);
+  k.MT = c.max_tracks ? c.max_tracks : k.T;
+  k.MC = c.max_track_clusters ? c.max_track_clusters : std::max<uint64_t>(1, c.max_clusters);
+  return k;
+}
+
+Layout layout_of(const Caps& k) {
+  Layout L{};
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = o;
+    o += (bytes + kAlign - 1) / kAlign * kAlign;
+    return at;
+  };
+  L.row_off = take((k.SRmax + 1) * 4);
+  L.rows = take((uint64_t)k.R * sizeof(RowConst));
+  L.secs = take((uint64_t)k.Smax * sizeof(SectorConst));
+  L.row_dims = take(k.SRmax * 4);
+  L.bin_start = take((k.N + 2 * k.SRmax + 2) * 4);
+  L.syz = take(k.N * 8);
+  L.sid = take(k.N * 4);
+  L.up0 = take(k.N * 4);
+  L.down0 = take(k.N * 4);
+  L.up1 = take(k.N * 4);
+  L.down1 = take(k.N * 4);
+  L.sflag = take(k.N);
+  L.row_nstart = take(k.SRmax * 4);
+  L.row_start_off = take((k.SRmax + 1) * 4);
+  L.start_pos = take(k.T * 4);
+  L.start_sr = take(k.T * 4);
+  L.tk_rowhit = take((uint64_t)k.R * k.T * 4);
+  L.tk_info = take(4 * k.T * 4);
+  L.tk_param = take(5 * k.T * 4);
+  L.tk_cov = take(15 * k.T * 4);
+  L.tk_chi2 = take(k.T * 4);
+  L.W = take(k.N * 8);
+  L.tk_pack = take(k.T * 8);
+  L.tk_scan = take((k.T + 1) * 8);
+  L.out_sector = take(k.MT * 4);
+  L.out_start = take(k.MT * 4);
+  L.out_first = take((k.MT + 1) * 4);
+  L.out_clusters = take(k.MC * 4);
+  L.out_xref = take(k.MT * 4);
+  L.out_param = take(5 * k.MT * 4);
+  L.out_cov = take(15 * k.MT * 4);
+  L.out_chi2 = take(k.MT * 4);
+  L.out_ndf = take(k.MT * 4);
+  L.scan_blocks = take((uint64_t)kScanMaxBlocks * 8);
+  L.hdr = take(sizeof(ResultHeader));
+  L.in_y = take(k.N * 4);
+  L.in_z = take(k.N * 4);
+  L.total = o;
+  return L;
+}
+
+std::string validate_config(const tpc_tracker_config* c) {
+  if (!c) return "config is NULL";
+  if (c->abi_version != TPC_ABI_VERSION) return "abi_version mismatch";
+  if (c->n_rows < 3 || c->n_rows > TPC_MAX_ROWS) return "n_rows out of range [3, 255]";
+  if (!c->row_x || !c->row_half_y) return "row_x / row_half_y is NULL";
+  for (int r = 0; r < c->n_rows; ++r) {
+    if (!std::isfinite(c->row_x[r]) || !std::isfinite(c->row_half_y[r]) || !(c->row_half_y[r] > 0.0))
+      return "row geometry not finite or half-width <= 0";
+    if (r > 0 && !(c->row_x[r] > c->row_x[r - 1])) return "row_x not strictly increasing";
+  }
+  if (!std::isfinite(c->bz_tesla)) return "bz not finite";
+  if (!(c->sigma_y > 0.0) || !(c->sigma_z > 0.0)) return "sigma_y/sigma_z must be > 0";
+  if (c->grid_hits_per_bin < 1) return "grid_hits_per_bin must be >= 1";
+  if (!(c->s_max > 0.0 && c->s_max < 1.0)) return "s_max must be in (0, 1)";
+  if (!(c->gate_nsigma > 0.0) || !(c->win_cap > 0.0) || !(c->seed_qpt_max > 0.0)) return "gate/cap/qpt_max must be > 0";
+  if (!(c->c0_sinphi > 0.0 && c->c0_tanl > 0.0 && c->c0_qpt > 0.0)) return "initial variances must be > 0";
+  if (c->max_miss < 0 || c->min_tracklet_hits < 3 || c->min_track_hits < 1) return "hit-count cuts out of range";
+  if (c->max_sectors < 1) return "max_sectors must be >= 1";
+  if (c->max_clusters >= (1ull << 31)) return "max_clusters must be < 2^31";
+  const Caps k = caps_of(*c);
+  if (k.T > (uint64_t)kScanBlock * kScanMaxBlocks) return "max_tracklets exceeds 8M";
+  if (k.SRmax + 1 > (uint64_t)kScanBlock * kScanMaxBlocks) return "max_sectors * n_rows too large";
+  if (k.MT >= (1ull << 32) || k.MC >= (1ull << 32)) return "output capacities must be < 2^32";
+  return "";
+}
+
+}  // namespace
+
+struct tpc_tracker {
+  tpc_tracker_config cfg{};
+  std::vector<double> row_x, row_half_y;
+  Caps caps{};
+  Layout lay{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* ws = nullptr;
+  bool own_ws = false;
+  DevPtrs d{};
+  KfConst kc{};
+  std::vector<RowConst> rows;
+  // pinned host memory
+  uint32_t* h_row_off = nullptr;
+  SectorConst* h_secs = nullptr;
+  ResultHeader* h_hdr = nullptr;
+  char* h_out = nullptr;      // all outputs, laid out like the device outputs
+  hipEvent_t done = nullptr;
+  hipEvent_t ev[kPasses + 1] = {};
+  bool timing = false;
+  bool timed_last = false;
+  // request state
+  uint64_t next_id = 1, cur_id = 0;
+  bool in_flight = false;
+  bool fetched = false;
+  uint32_t cur_S = 0, cur_N = 0;
+  tpc_tracks out{};
+};
+
+extern "C" {
+
+void tpc_default_config(tpc_tracker_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof *c);
+  c->abi_version = TPC_ABI_VERSION;
+  c->n_rows = 152;
+  c->bz_tesla = 0.5;
+  c->sigma_y = 0.1;
+  c->sigma_z = 0.15;
+  c->grid_hits_per_bin = 2;
+  c->win_a_y = 2.0;
+  c->win_b_y = 0.5;
+  c->win_a_z = 2.0;
+  c->win_b_z = 0.7;
+  c->link_nsigma = 4.0;
+  c->s_max = 0.99;
+  c->seed_qpt_max = 10.0;
+  c->c0_sinphi = 0.25;
+  c->c0_tanl = 0.25;
+  c->c0_qpt = 25.0;
+  c->gate_nsigma = 3.0;
+  c->win_cap = 3.0;
+  c->edge_margin = 1.0;
+  c->max_miss = 5;
+  c->min_tracklet_hits = 10;
+  c->min_track_hits = 10;
+  c->min_owned_frac = 0.5;
+  c->max_sectors = 36;
+  c->max_clusters = 2000000;
+  c->device = 0;
+}
+
+uint64_t tpc_workspace_bytes(const tpc_tracker_config* cfg) {
+  if (!validate_config(cfg).empty()) return 0;
+  return layout_of(caps_of(*cfg)).total;
+}
+
+const char* tpc_last_error(void) { return g_last_error.c_str(); }
+
+tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) {
+  if (!out) return fail(TPC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  const std::string why = validate_config(cfg);
+  if (!why.empty()) return fail(TPC_E_INVAL, why);
+  const Caps caps = caps_of(*cfg);
+  const Layout lay = layout_of(caps);
+  if (cfg->workspace && cfg->workspace_bytes < lay.total) return fail(TPC_E_INVAL, "workspace too small");
+  if (cfg->workspace && ((uintptr_t)cfg->workspace % kAlign)) return fail(TPC_E_INVAL, "workspace not 256-byte aligned");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(TPC_E_INVAL, "device ordinal out of range");
+  HIP_TRY(hipSetDevice(cfg->device));
+  tpc_tracker* t = new tpc_tracker();
+  t->cfg = *cfg;
+  t->row_x.assign(cfg->row_x, cfg->row_x + cfg->n_rows);
+  t->row_half_y.assign(cfg->row_half_y, cfg->row_half_y + cfg->n_rows);
+  t->cfg.row_x = t->row_x.data();
+  t->cfg.row_half_y = t->row_half_y.data();
+  t->caps = caps;
+  t->lay = lay;
+  t->device = cfg->device;
+  auto cleanup = [&](tpc_status st) {
+    tpc_tracker_destroy(t);
+    return st;
+  };
+  if (cfg->stream) {
+    t->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&t->stream, hipStreamNonBlocking) != hipSuccess)
+      return cleanup(fail(TPC_E_DEVICE, "hipStreamCreate failed"));
+    t->own_stream = true;
+  }
+  if (cfg->workspace) {
+    t->ws = (char*)cfg->workspace;
+  } else {
+    if (hipMalloc((void**)&t->ws, lay.total) != hipSuccess) return cleanup(fail(TPC_E_NOMEM, "hipMalloc workspace"));
+    t->own_ws = true;
+  }
+  // constant tables: double arithmetic, one rounding to float32
+  const uint32_t R = caps.R;
+  t->rows.resize(R);
+  for (uint32_t r = 0; r < R; ++r) {
+    RowConst& c = t->rows[r];
+    std::memset(&c, 0, sizeof c);
+    const double X = t->row_x[r], Y = t->row_half_y[r];
+    c.x = (float)X;
+    c.half_y = (float)Y;
+    c.y_lo = (float)(-Y);
+    c.inv_wy = (float)(1.0 / (2.0 * Y));
+    c.ly = (int32_t)std::ceil(20.0 * Y);
+    if (r >= 1 && r + 1 < R) {
+      const double du = t->row_x[r + 1] - X, dd = X - t->row_x[r - 1];
+      const double tt = dd / (dd + du);
+      c.t = (float)tt;
+      c.wy_up = (float)(cfg->win_a_y * du + cfg->win_b_y);
+      c.wz_up = (float)(cfg->win_a_z * du + cfg->win_b_z);
+      c.wy_dn = (float)(cfg->win_a_y * dd + cfg->win_b_y);
+      c.wz_dn = (float)(cfg->win_a_z * dd + cfg->win_b_z);
+      const double n2 = cfg->link_nsigma * cfg->link_nsigma, s2 = cfg->sigma_y * cfg->sigma_y;
+      c.dmax = (float)((n2 * s2) * ((1.0 + tt * tt) + (1.0 - tt) * (1.0 - tt)));
+    }
+  }
+  KfConst& k = t->kc;
+  k.bk = (float)(-kCB * cfg->bz_tesla);
+  k.s_max = (float)cfg->s_max;
+  k.qpt_max = (float)cfg->seed_qpt_max;
+  k.vy = (float)(cfg->sigma_y * cfg->sigma_y);
+  k.vz = (float)(cfg->sigma_z * cfg->sigma_z);
+  k.c0_sinphi = (float)cfg->c0_sinphi;
+  k.c0_tanl = (float)cfg->c0_tanl;
+  k.c0_qpt = (float)cfg->c0_qpt;
+  k.gate = (float)cfg->gate_nsigma;
+  k.cap = (float)cfg->win_cap;
+  k.margin = (float)cfg->edge_margin;
+  const double ry = cfg->sigma_y / cfg->sigma_z;
+  k.rho = (float)(ry * ry);
+  k.min_owned_frac = (float)cfg->min_owned_frac;
+  k.max_miss = cfg->max_miss;
+  k.min_tracklet_hits = cfg->min_tracklet_hits;
+  k.min_track_hits = cfg->min_track_hits;
+  k.grid_k = cfg->grid_hits_per_bin;
+  k.n_rows = cfg->n_rows;
+  // device pointers
+  DevPtrs& d = t->d;
+  char* w = t->ws;
+  d.row_off = (const uint32_t*)(w + lay.row_off);
+  d.rows = (const RowConst*)(w + lay.rows);
+  d.secs = (const SectorConst*)(w + lay.secs);
+  d.row_dims = (uint32_t*)(w + lay.row_dims);
+  d.bin_start = (uint32_t*)(w + lay.bin_start);
+  d.syz = (float2*)(w + lay.syz);
+  d.sid = (uint32_t*)(w + lay.sid);
+  d.up0 = (int32_t*)(w + lay.up0);
+  d.down0 = (int32_t*)(w + lay.down0);
+  d.up1 = (int32_t*)(w + lay.up1);
+  d.down1 = (int32_t*)(w + lay.down1);
+  d.sflag = (uint8_t*)(w + lay.sflag);
+  d.row_nstart = (uint32_t*)(w + lay.row_nstart);
+  d.row_start_off = (uint32_t*)(w + lay.row_start_off);
+  d.start_pos = (uint32_t*)(w + lay.start_pos);
+  d.start_sr = (uint32_t*)(w + lay.start_sr);
+  d.tk_rowhit = (int32_t*)(w + lay.tk_rowhit);
+  d.tk_info = (int32_t*)(w + lay.tk_info);
+  d.tk_param = (float*)(w + lay.tk_param);
+  d.tk_cov = (float*)(w + lay.tk_cov);
+  d.tk_chi2 = (float*)(w + lay.tk_chi2);
+  d.W = (unsigned long long*)(w + lay.W);
+  d.tk_pack = (unsigned long long*)(w + lay.tk_pack);
+  d.tk_scan = (unsigned long long*)(w + lay.tk_scan);
+  d.out_sector = (uint32_t*)(w + lay.out_sector);
+  d.out_start = (uint32_t*)(w + lay.out_start);
+  d.out_first = (uint32_t*)(w + lay.out_first);
+  d.out_clusters = (uint32_t*)(w + lay.out_clusters);
+  d.out_xref = (float*)(w + lay.out_xref);
+  d.out_param = (float*)(w + lay.out_param);
+  d.out_cov = (float*)(w + lay.out_cov);
+  d.out_chi2 = (float*)(w + lay.out_chi2);
+  d.out_ndf = (int32_t*)(w + lay.out_ndf);
+  d.scan_blocks = (unsigned long long*)(w + lay.scan_blocks);
+  d.hdr = (ResultHeader*)(w + lay.hdr);
+  d.grid_k = cfg->grid_hits_per_bin;
+  d.rho = k.rho;
+  d.R = R;
+  d.tcap = (uint32_t)caps.T;
+  d.max_tracks = (uint32_t)caps.MT;
+  d.max_track_clusters = caps.MC;
+  // pinned host buffers
+  if (hipHostMalloc((void**)&t->h_row_off, (caps.SRmax + 1) * 4) != hipSuccess ||
+      hipHostMalloc((void**)&t->h_secs, caps.Smax * sizeof(SectorConst)) != hipSuccess ||
+      hipHostMalloc((void**)&t->h_hdr, sizeof(ResultHeader)) != hipSuccess)
+    return cleanup(fail(TPC_E_NOMEM, "hipHostMalloc staging"));
+  const uint64_t out_bytes = lay.out_ndf + caps.MT * 4 - lay.out_sector;
+  if (hipHostMalloc((void**)&t->h_out, out_bytes) != hipSuccess)
+    return cleanup(fail(TPC_E_NOMEM, "hipHostMalloc outputs"));
+  if (hipMemcpy((void*)d.rows, t->rows.data(), R * sizeof(RowConst), hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(TPC_E_DEVICE, "upload row constants"));
+  if (hipEventCreateWithFlags(&t->done, hipEventDisableTiming) != hipSuccess)
+    return cleanup(fail(TPC_E_DEVICE, "hipEventCreate"));
+  for (int i = 0; i <= kPasses; ++i)
+    if (hipEventCreate(&t->ev[i]) != hipSuccess) return cleanup(fail(TPC_E_DEVICE, "hipEventCreate"));
+  *out = t;
+  g_last_error.clear();
+  return TPC_OK;
+}
+
+void tpc_tracker_destroy(tpc_tracker* t) {
+  if (!t) return;
+  // teardown: errors here cannot be reported to anyone, so they are ignored
+  (void)hipSetDevice(t->device);
+  if (t->in_flight && t->done) (void)hipEventSynchronize(t->done);
+  if (t->stream) (void)hipStreamSynchronize(t->stream);
+  if (t->done) (void)hipEventDestroy(t->done);
+  for (auto& e : t->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (t->own_ws && t->ws) (void)hipFree(t->ws);
+  if (t->h_row_off) (void)hipHostFree(t->h_row_off);
+  if (t->h_secs) (void)hipHostFree(t->h_secs);
+  if (t->h_hdr) (void)hipHostFree(t->h_hdr);
+  if (t->h_out) (void)hipHostFree(t->h_out);
+  if (t->own_stream && t->stream) (void)hipStreamDestroy(t->stream);
+  delete t;
+}
+
+}  // extern "C"
+
+namespace {
+
+__global__ void k_begin(ResultHeader* h) {
+  h->n_starts = 0;
+  h->error_flags = 0;
+  h->n_tracks = 0;
+  h->pad0 = 0;
+  h->n_track_clusters = 0;
+  h->n_steps = 0;
+}
+
+std::string validate_frame(const tpc_tracker* t, const tpc_timeframe* f, uint32_t* max_row) {
+  if (!f) return "timeframe is NULL";
+  if (f->n_rows != (uint32_t)t->cfg.n_rows) return "n_rows differs from the configuration";
+  if (f->n_sectors < 1 || f->n_sectors > t->caps.Smax) return "n_sectors out of range";
+  if (f->n_clusters > t->caps.N) return "n_clusters exceeds max_clusters";
+  if (!f->row_offsets || !f->sector_z_lo || !f->sector_z_hi) return "row_offsets / sector z ranges are NULL";
+  if (f->n_clusters && (!f->y || !f->z)) return "y / z is NULL";
+  if (f->flags & ~1u) return "unknown flags";
+  const uint64_t SR = (uint64_t)f->n_sectors * f->n_rows;
+  if (f->row_offsets[0] != 0) return "row_offsets[0] != 0";
+  uint32_t mx = 0;
+  for (uint64_t i = 0; i < SR; ++i) {
+    if (f->row_offsets[i + 1] < f->row_offsets[i]) return "row_offsets not non-decreasing";
+    mx = std::max(mx, f->row_offsets[i + 1] - f->row_offsets[i]);
+  }
+  if (f->row_offsets[SR] != f->n_clusters) return "row_offsets does not end at n_clusters";
+  if (mx > TPC_MAX_ROW_HITS) return "a row holds more than 65535 clusters";
+  for (uint32_t s = 0; s < f->n_sectors; ++s) {
+    const float lo = f->sector_z_lo[s], hi = f->sector_z_hi[s];
+    if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo) || std::fabs(lo) > TPC_MAX_COORD ||
+        std::fabs(hi) > TPC_MAX_COORD)
+      return "sector z range invalid";
+  }
+  *max_row = mx;
+  return "";
+}
+
+}  // namespace
+
+extern "C" {
+
+tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t* request_id) {
+  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
+  if (t->in_flight) return fail(TPC_E_BUSY, "previous request not released");
+  uint32_t max_row = 0;
+  const std::string why = validate_frame(t, f, &max_row);
+  if (!why.empty()) return fail(TPC_E_INVAL, why);
+  HIP_TRY(hipSetDevice(t->device));
+  DevPtrs& d = t->d;
+  const uint32_t S = f->n_sectors, R = f->n_rows, SR = S * R, N = (uint32_t)f->n_clusters;
+  d.S = S;
+  d.SR = SR;
+  d.N = N;
+  std::memcpy(t->h_row_off, f->row_offsets, (SR + 1) * sizeof(uint32_t));
+  for (uint32_t s = 0; s < S; ++s) {
+    SectorConst& c = t->h_secs[s];
+    const double w = (double)f->sector_z_hi[s] - (double)f->sector_z_lo[s];
+    c.z_lo = f->sector_z_lo[s];
+    c.inv_wz = (float)(1.0 / w);
+    c.lz = (int32_t)std::ceil(10.0 * w);
+    c.pad = 0;
+  }
+  hipStream_t st = t->stream;   // the previous request was released, so the staging buffers are free
+  HIP_TRY(hipMemcpyAsync((void*)d.row_off, t->h_row_off, (SR + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync((void*)d.secs, t->h_secs, S * sizeof(SectorConst), hipMemcpyHostToDevice, st));
+  if (f->flags & TPC_IN_HOST) {
+    d.y = (const float*)(t->ws + t->lay.in_y);
+    d.z = (const float*)(t->ws + t->lay.in_z);
+    if (N) {
+      HIP_TRY(hipMemcpyAsync((void*)d.y, f->y, (size_t)N * 4, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync((void*)d.z, f->z, (size_t)N * 4, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));   // host arrays may be released on return
+    }
+  } else {
+    d.y = f->y;
+    d.z = f->z;
+  }
+  const bool tm = t->timing;
+  if (tm) HIP_TRY(hipEventRecord(t->ev[0], st));
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, st, d.hdr);
+  launch_grid(d, max_row, st);
+  if (tm) HIP_TRY(hipEventRecord(t->ev[1], st));
+  launch_links(d, max_row, st);
+  if (tm) HIP_TRY(hipEventRecord(t->ev[2], st));
+  launch_clean_starts(d, max_row, st);
+  if (tm) HIP_TRY(hipEventRecord(t->ev[3], st));
+  launch_tracklets(d, t->kc, st);
+  if (tm) HIP_TRY(hipEventRecord(t->ev[4], st));
+  launch_select(d, t->kc, st);
+  if (tm) HIP_TRY(hipEventRecord(t->ev[5], st));
+  HIP_TRY(hipMemcpyAsync(t->h_hdr, d.hdr, sizeof(ResultHeader), hipMemcpyDeviceToHost, st));
+  if (tm) HIP_TRY(hipEventRecord(t->ev[6], st));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(t->done, st));
+  t->timed_last = tm;
+  t->cur_id = t->next_id++;
+  t->in_flight = true;
+  t->fetched = false;
+  t->cur_S = S;
+  t->cur_N = N;
+  if (request_id) *request_id = t->cur_id;
+  return TPC_OK;
+}
+
+tpc_status tpc_get_tracks(tpc_tracker* t, uint64_t request_id, int32_t blocking, tpc_tracks* out) {
+  if (!t || !out) return fail(TPC_E_INVAL, "NULL argument");
+  if (!t->in_flight || request_id != t->cur_id) return fail(TPC_E_INVAL, "unknown request id");
+  HIP_TRY(hipSetDevice(t->device));
+  if (!blocking) {
+    hipError_t q = hipEventQuery(t->done);
+    if (q == hipErrorNotReady) return fail(TPC_E_NOTREADY, "request still running");
+    if (q != hipSuccess) return fail(TPC_E_DEVICE, hipGetErrorString(q));
+  }
+  HIP_TRY(hipEventSynchronize(t->done));
+  std::memset(out, 0, sizeof *out);
+  const ResultHeader h = *t->h_hdr;
+  out->error_flags = h.error_flags;
+  out->n_tracklets = h.n_starts;
+  out->n_steps = h.n_steps;
+  if (h.error_flags & TPC_ERR_NONFINITE) return fail(TPC_E_INPUT, "non-finite or out-of-range cluster coordinate");
+  if (h.error_flags) return fail(TPC_E_CAPACITY, "capacity exceeded (see error_flags)");
+  const DevPtrs& d = t->d;
+  const Layout& L = t->lay;
+  char* ho = t->h_out;
+  auto host = [&](uint64_t off) { return ho + (off - L.out_sector); };
+  if (!t->fetched) {
+    const uint32_t n = h.n_tracks;
+    const uint64_t nc = h.n_track_clusters;
+    hipStream_t st = t->stream;
+    struct {
+      const void* src;
+      uint64_t off, bytes;
+    } cp[] = {
+        {d.out_sector, L.out_sector, n * 4ull},      {d.out_start, L.out_start, n * 4ull},
+        {d.out_first, L.out_first, (n + 1) * 4ull},  {d.out_clusters, L.out_clusters, nc * 4},
+        {d.out_xref, L.out_xref, n * 4ull},          {d.out_param, L.out_param, n * 20ull},
+        {d.out_cov, L.out_cov, n * 60ull},           {d.out_chi2, L.out_chi2, n * 4ull},
+        {d.out_ndf, L.out_ndf, n * 4ull},
+    };
+    for (auto& c : cp)
+      if (c.bytes) HIP_TRY(hipMemcpyAsync(host(c.off), c.src, c.bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    t->fetched = true;
+  }
+  out->n_tracks = h.n_tracks;
+  out->n_track_clusters = h.n_track_clusters;
+  out->track_sector = (const uint32_t*)host(L.out_sector);
+  out->track_start = (const uint32_t*)host(L.out_start);
+  out->track_first = (const uint32_t*)host(L.out_first);
+  out->cluster_ids = (const uint32_t*)host(L.out_clusters);
+  out->x_ref = (const float*)host(L.out_xref);
+  out->param = (const float*)host(L.out_param);
+  out->cov = (const float*)host(L.out_cov);
+  out->chi2 = (const float*)host(L.out_chi2);
+  out->ndf = (const int32_t*)host(L.out_ndf);
+  return TPC_OK;
+}
+
+tpc_status tpc_release(tpc_tracker* t, uint64_t request_id) {
+  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
+  if (!t->in_flight || request_id != t->cur_id) return fail(TPC_E_INVAL, "unknown request id");
+  HIP_TRY(hipSetDevice(t->device));
+  HIP_TRY(hipEventSynchronize(t->done));
+  t->in_flight = false;
+  return TPC_OK;
+}
+
+tpc_status tpc_debug_copy(tpc_tracker* t, int32_t what, void* dst, uint64_t cap, uint64_t* bytes) {
+  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
+  HIP_TRY(hipSetDevice(t->device));
+  HIP_TRY(hipStreamSynchronize(t->stream));
+  const DevPtrs& d = t->d;
+  const uint64_t N = t->cur_N, SR = (uint64_t)t->cur_S * t->caps.R, T = t->caps.T;
+  const uint64_t ns = std::min<uint64_t>(t->h_hdr->n_starts, T);
+  const void* src = nullptr;
+  uint64_t n = 0;
+  switch (what) {
+    case TPC_DBG_SORTED_ID: src = d.sid; n = N * 4; break;
+    case TPC_DBG_SORTED_YZ: src = d.syz; n = N * 8; break;
+    case TPC_DBG_BIN_START: src = d.bin_start; n = (N + 2 * SR) * 4; break;
+    case TPC_DBG_ROW_DIMS: src = d.row_dims; n = SR * 4; break;
+    case TPC_DBG_UP0: src = d.up0; n = N * 4; break;
+    case TPC_DBG_DOWN0: src = d.down0; n = N * 4; break;
+    case TPC_DBG_UP1: src = d.up1; n = N * 4; break;
+    case TPC_DBG_DOWN1: src = d.down1; n = N * 4; break;
+    case TPC_DBG_STARTS: src = d.start_pos; n = ns * 4; break;
+    case TPC_DBG_TK_ROWHIT: src = d.tk_rowhit; n = (uint64_t)t->caps.R * T * 4; break;
+    case TPC_DBG_TK_INFO: src = d.tk_info; n = 4 * T * 4; break;
+    case TPC_DBG_TK_PARAM: src = d.tk_param; n = 5 * T * 4; break;
+    case TPC_DBG_TK_COV: src = d.tk_cov; n = 15 * T * 4; break;
+    case TPC_DBG_TK_CHI2: src = d.tk_chi2; n = ns * 4; break;
+    default: return fail(TPC_E_INVAL, "unknown debug array");
+  }
+  if (bytes) *bytes = n;
+  if (dst && n) HIP_TRY(hipMemcpy(dst, src, std::min(cap, n), hipMemcpyDeviceToHost));
+  return TPC_OK;
+}
+
+tpc_status tpc_set_timing(tpc_tracker* t, int32_t enable) {
+  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
+  t->timing = enable != 0;
+  return TPC_OK;
+}
+
+tpc_status tpc_get_pass_times(tpc_tracker* t, float* ms, int32_t n) {
+  if (!t || !ms) return fail(TPC_E_INVAL, "NULL argument");
+  if (!t->timed_last) return fail(TPC_E_INVAL, "timing was off for the last request");
+  HIP_TRY(hipSetDevice(t->device));
+  HIP_TRY(hipEventSynchronize(t->ev[kPasses]));
+  for (int i = 0; i < n && i < kPasses; ++i) HIP_TRY(hipEventElapsedTime(&ms[i], t->ev[i], t->ev[i + 1]));
+  return TPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+// K5: tracklet constructor -- step C5 of the tracker definition.
+//
+// One lane per tracklet (chain start).  The helix state p[5] and packed
+// covariance C[15] live in float32 registers; the transport exploits the
+// sparsity of the Jacobian (6 non-trivial entries).  The lane walks its chain
+// (dependent up1 gathers), seeds from three chain hits, fits the chain,
+// extends outward through the row grids and refits inward with a fresh
+// covariance, filling gaps and extending below the chain.
+//
+// The per-tracklet row -> hit column lives in global memory (row-major over
+// tracklets, so lanes at the same row write one coalesced segment); the
+// downward pass rewrites every row in [x_ref row, outermost row] with its
+// final value, which is the only range the selector reads.
+#include "device_common.h"
+
+namespace tpc {
+namespace {
+
+constexpr int kThreads = 64;
+
+__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }   // i >= j
+
+struct Trk {
+  float p[5];
+  float c[15];
+};
+
+// asin(u)/u and d/du of it; |u| is below 0.02 for row-to-row steps.
+__device__ __forceinline__ float asin_over(float u) {
+  const float u2 = u * u;
+  if (fabsf(u) < 0.05f) return 1.0f + u2 * (1.0f / 6.0f + u2 * (3.0f / 40.0f + u2 * (5.0f / 112.0f)));
+  return asinf(u) / u;
+}
+__device__ __forceinline__ float asin_over_prime(float u) {
+  const float u2 = u * u;
+  if (fabsf(u) < 0.1f)
+    return u * (1.0f / 3.0f + u2 * (3.0f / 10.0f + u2 * (15.0f / 56.0f + u2 * (35.0f / 144.0f))));
+  return (u / sqrtf(1.0f - u2) - asinf(u)) / u2;
+}
+
+// Helix transport from x to x + dx with covariance; false on |sin phi| >= s_max or |u| >= 1.
+__device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
+  const float s1 = t.p[2], tl = t.p[3], qp = t.p[4];
+  const float kap = k.bk * qp;
+  if (!(fabsf(s1) < k.s_max)) return false;
+  const float s2 = s1 + kap * dx;
+  if (!(fabsf(s2) < k.s_max)) return false;
+  const float c1 = sqrtf((1.0f - s1) * (1.0f + s1));
+  const float c2 = sqrtf((1.0f - s2) * (1.0f + s2));
+  const float ic = 1.0f / (c1 + c2);
+  const float dy = dx * ((s1 + s2) * ic);
+  const float L = sqrtf(dx * dx + dy * dy);
+  const float u = 0.5f * kap * L;
+  if (!(fabsf(u) < 1.0f)) return false;
+  const float sgn = dx >= 0.0f ? 1.0f : -1.0f;
+  const float S = sgn * L * asin_over(u);
+  // Jacobian entries (exact derivative of the map above)
+  const float D = (1.0f + c1 * c2 + s1 * s2) * (ic * ic);
+  const float ddy_ds1 = dx * D * (1.0f / c1 + 1.0f / c2);
+  const float ddy_dk = dx * dx * (D / c2) * k.bk;
+  const float dS_dL = sgn / sqrtf(1.0f - u * u);
+  const float dS_dkap = sgn * 0.5f * L * L * asin_over_prime(u);
+  const float dL_ddy = L > 0.0f ? dy / L : 0.0f;
+  const float A = ddy_ds1;                                // F02
+  const float B = ddy_dk;                                 // F04
+  const float Cc = tl * dS_dL * dL_ddy * ddy_ds1;         // F12
+  const float Dd = S;                                     // F13
+  const float E = tl * (dS_dL * dL_ddy * ddy_dk + dS_dkap * k.bk);  // F14
+  const float Fk = k.bk * dx;                             // F24
+  t.p[0] += dy;
+  t.p[1] += tl * S;
+  t.p[2] = s2;
+  // C' = F C F^T with F = I + {02:A, 04:B, 12:Cc, 13:Dd, 14:E, 24:Fk}
+  float* c = t.c;
+  float M[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) M[i][j] = i >= j ? c[tri(i, j)] : c[tri(j, i)];
+  float G[5][5];   // G = F C
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    G[0][j] = M[0][j] + A * M[2][j] + B * M[4][j];
+    G[1][j] = M[1][j] + Cc * M[2][j] + Dd * M[3][j] + E * M[4][j];
+    G[2][j] = M[2][j] + Fk * M[4][j];
+    G[3][j] = M[3][j];
+    G[4][j] = M[4][j];
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {   // C'_ij = sum_k G_ik F_jk
+    const float g0 = G[i][0], g1 = G[i][1], g2 = G[i][2], g3 = G[i][3], g4 = G[i][4];
+    const float r0 = g0 + A * g2 + B * g4;
+    const float r1 = g1 + Cc * g2 + Dd * g3 + E * g4;
+    const float r2 = g2 + Fk * g4;
+    const float rr[5] = {r0, r1, r2, g3, g4};
+#pragma unroll
+    for (int j = 0; j <= i; ++j) c[tri(i, j)] = rr[j];
+  }
+  return true;
+}
+
+// Kalman update with a measurement of (y, z).
+__device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst& k, float& chi2) {
+  float* c = t.c;
+  const float r0 = ym - t.p[0], r1 = zm - t.p[1];
+  const float S00 = c[0] + k.vy, S01 = c[1], S11 = c[2] + k.vz;
+  const float id = 1.0f / (S00 * S11 - S01 * S01);
+  const float I00 = S11 * id, I01 = -S01 * id, I11 = S00 * id;
+  float c0[5], c1[5];   // rows 0 and 1 of C (C_i0, C_i1)
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    c0[i] = i >= 0 ? c[tri(i, 0)] : 0.0f;
+    c1[i] = i >= 1 ? c[tri(i, 1)] : c[tri(1, 0)];
+  }
+  float K0[5], K1[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    K0[i] = c0[i] * I00 + c1[i] * I01;
+    K1[i] = c0[i] * I01 + c1[i] * I11;
+    t.p[i] += K0[i] * r0 + K1[i] * r1;
+  }
+  // Joseph form: C' = (I - K H) C (I - K H)^T + K V K^T, evaluated on the packed triangle.
+  // P = (I - K H) C; only rows of C enter, and H picks columns 0 and 1.
+  float P[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const float cij = i >= j ? c[tri(i, j)] : c[tri(j, i)];
+      P[i][j] = cij - K0[i] * c0[j] - K1[i] * c1[j];
+    }
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j)
+      c[tri(i, j)] = P[i][j] - P[i][0] * K0[j] - P[i][1] * K1[j] + K0[i] * k.vy * K0[j] + K1[i] * k.vz * K1[j];
+  chi2 += r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);
+}
+
+__device__ __forceinline__ void set_c0(Trk& t, const KfConst& k) {
+#pragma unroll
+  for (int i = 0; i < 15; ++i) t.c[i] = 0.0f;
+  t.c[tri(0, 0)] = k.vy;
+  t.c[tri(1, 1)] = k.vz;
+  t.c[tri(2, 2)] = k.c0_sinphi;
+  t.c[tri(3, 3)] = k.c0_tanl;
+  t.c[tri(4, 4)] = k.c0_qpt;
+}
+
+// Grid search in row sr for the candidate closest to (yp, zp); -1 if none.
+__device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const RowConst& rc, const SectorConst& sc,
+                                          const Trk& t, const KfConst& k) {
+  const float sy2 = t.c[0] + k.vy, sz2 = t.c[2] + k.vz;
+  const float wy = fminf(k.gate * sqrtf(sy2), k.cap), wz = fminf(k.gate * sqrtf(sz2), k.cap);
+  const float isy = 1.0f / sy2, isz = 1.0f / sz2;
+  const float yp = t.p[0], zp = t.p[1];
+  const uint32_t dims = d.row_dims[sr];
+  const int ny = (int)(dims & 0xFFFFu), nz = (int)(dims >> 16);
+  const int iy0 = bin1((yp - wy) - kWinPad, rc.y_lo, rc.inv_wy, ny);
+  const int iy1 = bin1((yp + wy) + kWinPad, rc.y_lo, rc.inv_wy, ny);
+  const int iz0 = bin1((zp - wz) - kWinPad, sc.z_lo, sc.inv_wz, nz);
+  const int iz1 = bin1((zp + wz) + kWinPad, sc.z_lo, sc.inv_wz, nz);
+  const uint32_t* bs = d.bin_start + bin_base(d, sr);
+  int32_t best = -1;
+  float bd = 0.0f;
+  for (int iz = iz0; iz <= iz1; ++iz) {
+    const uint32_t lo = bs[iz * ny + iy0], hi = bs[iz * ny + iy1 + 1];
+    for (uint32_t q = lo; q < hi; ++q) {
+      const float2 h = d.syz[q];
+      const float dy = h.x - yp, dz = h.y - zp;
+      if (!(fabsf(dy) <= wy && fabsf(dz) <= wz)) continue;
+      const float dd = dy * dy * isy + dz * dz * isz;
+      if (best < 0 || dd < bd) {
+        best = (int32_t)q;
+        bd = dd;
+      }
+    }
+  }
+  return best;
+}
+
+// Three-point seed; false on failure.
+__device__ __forceinline__ bool seed3(float x0, float2 h0, float xm, float2 hm, float xl, float2 hl, const KfConst& k,
+                                      Trk& t) {
+  const float ax = xm - x0, ay = hm.x - h0.x, bx = xl - xm, by = hl.x - hm.x, cx = xl - x0, cy = hl.x - h0.x;
+  const float cross = ax * by - ay * bx;
+  const float la = sqrtf(ax * ax + ay * ay), lb = sqrtf(bx * bx + by * by), lc = sqrtf(cx * cx + cy * cy);
+  if (!(la > 0.0f && lb > 0.0f && lc > 0.0f)) return false;
+  const float kap = 2.0f * cross / (la * lb * lc);
+  const float u = 0.5f * kap * lc;
+  if (!(fabsf(u) < 1.0f)) return false;
+  const float phi0 = atan2f(cy, cx) - asinf(u);
+  const float s0l = lc * asin_over(u);
+  float qpt = k.bk != 0.0f ? kap / k.bk : 0.0f;
+  qpt = fminf(k.qpt_max, fmaxf(-k.qpt_max, qpt));
+  float sp, cp;
+  sincosf(phi0, &sp, &cp);
+  t.p[0] = h0.x;
+  t.p[1] = h0.y;
+  t.p[2] = sp;
+  t.p[3] = (hl.y - h0.y) / s0l;
+  t.p[4] = qpt;
+  return cp > 0.0f && fabsf(sp) < k.s_max;
+}
+
+__global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
+  const uint32_t nt = min(d.hdr->n_starts, d.tcap);
+  const uint32_t R = d.R, T = d.tcap;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
+    const uint32_t sr0 = d.start_sr[i];
+    const uint32_t sec = sr0 / R, r0 = sr0 % R, srb = sec * R;
+    const SectorConst sc = d.secs[sec];
+    int32_t* H = d.tk_rowhit + i;     // row r at H[r * T]
+    // chain walk
+    int32_t p = (int32_t)d.start_pos[i];
+    uint32_t n = 0;
+    int32_t plast = p;
+    while (p >= 0 && r0 + n < R) {   // links step one row outward, so a chain ends before row R
+      H[(size_t)(r0 + n) * T] = p;
+      plast = p;
+      ++n;
+      p = d.up1[p];
+    }
+    const uint32_t m = (n - 1) / 2, rl = r0 + n - 1;
+    const int32_t pm = H[(size_t)(r0 + m) * T];
+    Trk t;
+    const float2 h0 = d.syz[d.start_pos[i]];
+    if (!seed3(d.rows[r0].x, h0, d.rows[r0 + m].x, d.syz[pm], d.rows[rl].x, d.syz[plast], k, t)) {
+      d.tk_info[i] = -1;
+      continue;
+    }
+    set_c0(t, k);
+    float chi2 = 0.0f;
+    bool ok = true;
+    float xprev = d.rows[r0].x;
+    // chain fit (no gate)
+    for (uint32_t r = r0 + 1; r <= rl; ++r) {
+      const float x = d.rows[r].x;
+      if (!propagate(t, x - xprev, k)) {
+        ok = false;
+        break;
+      }
+      xprev = x;
+      const float2 h = d.syz[H[(size_t)r * T]];
+      update(t, h.x, h.y, k, chi2);
+    }
+    if (!ok) {
+      d.tk_info[i] = -2;
+      continue;
+    }
+    uint32_t steps = n - 1;
+    // upward extension
+    float pout[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
+    uint32_t rout = rl;
+    int miss = 0;
+    for (uint32_t r = rl + 1; r < R; ++r) {
+      const RowConst rc = d.rows[r];
+      ++steps;
+      if (!propagate(t, rc.x - xprev, k)) break;
+      xprev = rc.x;
+      if (fabsf(t.p[0]) > rc.half_y + k.margin) break;
+      const int32_t h = search(d, srb + r, rc, sc, t, k);
+      H[(size_t)r * T] = h;
+      if (h >= 0) {
+        const float2 hm = d.syz[h];
+        update(t, hm.x, hm.y, k, chi2);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
+        rout = r;
+        miss = 0;
+      } else if (++miss > k.max_miss) {
+        break;
+      }
+    }
+    // downward refit from the outermost hit, fresh covariance
+    {
+      const float2 ho = d.syz[H[(size_t)rout * T]];
+#pragma unroll
+      for (int q = 2; q < 5; ++q) t.p[q] = pout[q];
+      t.p[0] = ho.x;
+      t.p[1] = ho.y;
+    }
+    set_c0(t, k);
+    chi2 = 0.0f;
+    int nh = 1;
+    Trk snap = t;
+    uint32_t rin = rout;
+    xprev = d.rows[rout].x;
+    miss = 0;
+    for (int r = (int)rout - 1; r >= 0; --r) {
+      const RowConst rc = d.rows[r];
+      ++steps;
+      if (!propagate(t, rc.x - xprev, k)) break;
+      xprev = rc.x;
+      const bool below = (uint32_t)r < r0;
+      if (below && fabsf(t.p[0]) > rc.half_y + k.margin) break;
+      int32_t h = below ? -1 : H[(size_t)r * T];
+      if (h < 0) h = search(d, srb + (uint32_t)r, rc, sc, t, k);
+      H[(size_t)r * T] = h;
+      if (h >= 0) {
+        const float2 hm = d.syz[h];
+        update(t, hm.x, hm.y, k, chi2);
+        ++nh;
+        snap = t;
+        rin = (uint32_t)r;
+        if (below) miss = 0;
+      } else if (below && ++miss > k.max_miss) {
+        break;
+      }
+    }
+    d.tk_info[i] = nh;
+    d.tk_info[T + i] = (int32_t)rin;
+    d.tk_info[2 * T + i] = (int32_t)rout;
+    d.tk_info[3 * T + i] = (int32_t)r0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) d.tk_param[(size_t)q * T + i] = snap.p[q];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) d.tk_cov[(size_t)q * T + i] = snap.c[q];
+    d.tk_chi2[i] = chi2;
+    atomicAdd(&d.hdr->n_steps, (unsigned long long)steps);
+  }
+}
+
+}  // namespace
+
+void launch_tracklets(const DevPtrs& d, const KfConst& k, hipStream_t s) {
+  if (d.tcap == 0) return;
+  uint32_t blocks = (d.tcap + kThreads - 1) / kThreads;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(kThreads), 0, s, d, k);
+}
+
+}  // namespace tpc

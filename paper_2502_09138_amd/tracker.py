@@ -1,0 +1,298 @@
+"""Python binding of the C ABI in include/tpc_tracker.h (argument marshalling only).
+
+Every step of the tracking runs in the HIP library ``libtpc_tracker.so``; this
+module only fills the C structs, hands over device pointers, and copies the
+returned views into numpy arrays.  PyTorch supplies device memory (the
+workspace and the cluster arrays) and the HIP stream.  There is no fallback:
+if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+from .config import TrackerConfig
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpc_tracker.so")
+
+TPC_ABI_VERSION = 1
+TPC_OK, TPC_E_INVAL, TPC_E_NOMEM, TPC_E_DEVICE, TPC_E_CAPACITY, TPC_E_NOTREADY, TPC_E_INPUT, TPC_E_BUSY = \
+    0, -1, -2, -3, -4, -5, -6, -7
+TPC_IN_DEVICE, TPC_IN_HOST = 0, 1
+(TPC_DBG_SORTED_ID, TPC_DBG_SORTED_YZ, TPC_DBG_BIN_START, TPC_DBG_ROW_DIMS, TPC_DBG_UP0, TPC_DBG_DOWN0, TPC_DBG_UP1,
+ TPC_DBG_DOWN1, TPC_DBG_STARTS, TPC_DBG_TK_ROWHIT, TPC_DBG_TK_INFO, TPC_DBG_TK_PARAM, TPC_DBG_TK_COV,
+ TPC_DBG_TK_CHI2) = range(1, 15)
+N_PASSES = 6
+PASS_NAMES = ("grid", "neighbours", "clean+starts", "tracklets", "select", "output")
+
+
+class TrackerError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tpc status {status}: {msg}")
+        self.status = status
+
+
+class _Config(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("n_rows", C.c_int32),
+        ("row_x", C.POINTER(C.c_double)), ("row_half_y", C.POINTER(C.c_double)),
+        ("bz_tesla", C.c_double), ("sigma_y", C.c_double), ("sigma_z", C.c_double),
+        ("grid_hits_per_bin", C.c_int32),
+        ("win_a_y", C.c_double), ("win_b_y", C.c_double), ("win_a_z", C.c_double), ("win_b_z", C.c_double),
+        ("link_nsigma", C.c_double), ("s_max", C.c_double), ("seed_qpt_max", C.c_double),
+        ("c0_sinphi", C.c_double), ("c0_tanl", C.c_double), ("c0_qpt", C.c_double),
+        ("gate_nsigma", C.c_double), ("win_cap", C.c_double), ("edge_margin", C.c_double),
+        ("max_miss", C.c_int32), ("min_tracklet_hits", C.c_int32), ("min_track_hits", C.c_int32),
+        ("min_owned_frac", C.c_double),
+        ("max_sectors", C.c_uint32), ("max_clusters", C.c_uint64), ("max_tracklets", C.c_uint64),
+        ("max_tracks", C.c_uint64), ("max_track_clusters", C.c_uint64),
+        ("device", C.c_int32), ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
+    ]
+
+
+class _Frame(C.Structure):
+    _fields_ = [
+        ("n_sectors", C.c_uint32), ("n_rows", C.c_uint32), ("row_offsets", C.POINTER(C.c_uint32)),
+        ("y", C.c_void_p), ("z", C.c_void_p), ("charge", C.c_void_p), ("n_clusters", C.c_uint64),
+        ("sector_z_lo", C.POINTER(C.c_float)), ("sector_z_hi", C.POINTER(C.c_float)), ("flags", C.c_uint32),
+    ]
+
+
+class _Tracks(C.Structure):
+    _fields_ = [
+        ("n_tracks", C.c_uint32), ("n_track_clusters", C.c_uint64),
+        ("track_sector", C.POINTER(C.c_uint32)), ("track_start", C.POINTER(C.c_uint32)),
+        ("track_first", C.POINTER(C.c_uint32)), ("cluster_ids", C.POINTER(C.c_uint32)),
+        ("x_ref", C.POINTER(C.c_float)), ("param", C.POINTER(C.c_float)), ("cov", C.POINTER(C.c_float)),
+        ("chi2", C.POINTER(C.c_float)), ("ndf", C.POINTER(C.c_int32)),
+        ("error_flags", C.c_uint32), ("n_tracklets", C.c_uint32), ("n_steps", C.c_uint64),
+    ]
+
+
+EXPORTED = ("tpc_default_config", "tpc_workspace_bytes", "tpc_tracker_create", "tpc_tracker_destroy",
+            "tpc_track_timeframe", "tpc_get_tracks", "tpc_release", "tpc_last_error", "tpc_debug_copy",
+            "tpc_set_timing", "tpc_get_pass_times")
+
+_lib = None
+
+
+def load():
+    """Load libtpc_tracker.so (built by ``paper_2502_09138_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(python -m paper_2502_09138_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    L.tpc_default_config.argtypes = [P(_Config)]
+    L.tpc_workspace_bytes.restype = C.c_uint64
+    L.tpc_workspace_bytes.argtypes = [P(_Config)]
+    L.tpc_tracker_create.restype = C.c_int32
+    L.tpc_tracker_create.argtypes = [P(_Config), P(C.c_void_p)]
+    L.tpc_tracker_destroy.argtypes = [C.c_void_p]
+    L.tpc_track_timeframe.restype = C.c_int32
+    L.tpc_track_timeframe.argtypes = [C.c_void_p, P(_Frame), P(C.c_uint64)]
+    L.tpc_get_tracks.restype = C.c_int32
+    L.tpc_get_tracks.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, P(_Tracks)]
+    L.tpc_release.restype = C.c_int32
+    L.tpc_release.argtypes = [C.c_void_p, C.c_uint64]
+    L.tpc_last_error.restype = C.c_char_p
+    L.tpc_debug_copy.restype = C.c_int32
+    L.tpc_debug_copy.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint64, P(C.c_uint64)]
+    L.tpc_set_timing.restype = C.c_int32
+    L.tpc_set_timing.argtypes = [C.c_void_p, C.c_int32]
+    L.tpc_get_pass_times.restype = C.c_int32
+    L.tpc_get_pass_times.argtypes = [C.c_void_p, P(C.c_float), C.c_int32]
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != TPC_OK:
+        raise TrackerError(st, load().tpc_last_error().decode())
+
+
+def make_config(cfg: TrackerConfig, *, max_clusters, max_sectors=36, max_tracklets=0, max_tracks=0,
+                max_track_clusters=0, device=0):
+    """Fill the C config struct; returns (struct, keep-alive arrays)."""
+    c = _Config()
+    load().tpc_default_config(C.byref(c))
+    row_x = np.ascontiguousarray(cfg.row_x, np.float64)
+    row_half_y = np.ascontiguousarray(cfg.row_half_y, np.float64)
+    c.n_rows = len(row_x)
+    c.row_x = row_x.ctypes.data_as(C.POINTER(C.c_double))
+    c.row_half_y = row_half_y.ctypes.data_as(C.POINTER(C.c_double))
+    c.bz_tesla = cfg.bz
+    for f in ("sigma_y", "sigma_z", "grid_hits_per_bin", "win_a_y", "win_b_y", "win_a_z", "win_b_z", "link_nsigma",
+              "s_max", "seed_qpt_max", "c0_sinphi", "c0_tanl", "c0_qpt", "gate_nsigma", "win_cap", "edge_margin",
+              "max_miss", "min_tracklet_hits", "min_track_hits", "min_owned_frac"):
+        setattr(c, f, getattr(cfg, f))
+    c.max_sectors = max_sectors
+    c.max_clusters = max_clusters
+    c.max_tracklets = max_tracklets
+    c.max_tracks = max_tracks
+    c.max_track_clusters = max_track_clusters
+    c.device = device
+    return c, (row_x, row_half_y)
+
+
+@dataclasses.dataclass
+class Tracks:
+    n_tracklets: int
+    error_flags: int
+    sector: np.ndarray
+    start: np.ndarray
+    first: np.ndarray
+    cluster_ids: np.ndarray
+    x_ref: np.ndarray
+    param: np.ndarray     # [n, 5]
+    cov: np.ndarray       # [n, 15]
+    chi2: np.ndarray
+    ndf: np.ndarray
+
+    @property
+    def n_tracks(self):
+        return len(self.sector)
+
+
+class Tracker:
+    """One tracker on one GPU; workspace and stream come from torch."""
+
+    def __init__(self, cfg: TrackerConfig | None = None, *, max_clusters, max_sectors=36, max_tracklets=0,
+                 max_tracks=0, max_track_clusters=0, device=0, stream=None):
+        import torch
+        self._torch = torch
+        L = load()
+        cfg = cfg or TrackerConfig()
+        self.cfg = cfg
+        self.R = len(cfg.row_x)
+        self.device = torch.device("cuda", device)
+        c, self._keep = make_config(cfg, max_clusters=max_clusters, max_sectors=max_sectors,
+                                    max_tracklets=max_tracklets, max_tracks=max_tracks,
+                                    max_track_clusters=max_track_clusters, device=device)
+        nbytes = L.tpc_workspace_bytes(C.byref(c))
+        if nbytes == 0:
+            raise TrackerError(TPC_E_INVAL, "invalid tracker configuration")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        c.workspace = (base + 255) // 256 * 256
+        c.workspace_bytes = nbytes
+        # the tracker's own stream (default priority); each submit orders it after torch's current stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        c.stream = self.stream.cuda_stream
+        self._h = C.c_void_p()
+        _check(L.tpc_tracker_create(C.byref(c), C.byref(self._h)))
+        self.workspace_bytes = nbytes
+        self._inputs = None
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().tpc_tracker_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- requests ----
+    def submit(self, y, z, row_offsets, z_lo, z_hi, *, host=False):
+        """Enqueue one time frame; y/z are CUDA float32 tensors (or numpy with host=True)."""
+        row_offsets = np.ascontiguousarray(row_offsets, np.uint32)
+        z_lo = np.ascontiguousarray(z_lo, np.float32)
+        z_hi = np.ascontiguousarray(z_hi, np.float32)
+        f = _Frame()
+        f.n_rows = self.R
+        f.n_sectors = (len(row_offsets) - 1) // self.R
+        f.row_offsets = row_offsets.ctypes.data_as(C.POINTER(C.c_uint32))
+        f.n_clusters = int(row_offsets[-1])
+        f.sector_z_lo = z_lo.ctypes.data_as(C.POINTER(C.c_float))
+        f.sector_z_hi = z_hi.ctypes.data_as(C.POINTER(C.c_float))
+        if host:
+            y = np.ascontiguousarray(y, np.float32)
+            z = np.ascontiguousarray(z, np.float32)
+            f.y, f.z = y.ctypes.data, z.ctypes.data
+            f.flags = TPC_IN_HOST
+        else:
+            assert y.is_cuda and z.is_cuda and y.dtype == self._torch.float32 and z.dtype == self._torch.float32
+            assert y.is_contiguous() and z.is_contiguous()
+            self.stream.wait_stream(self._torch.cuda.current_stream(self.device))
+            y.record_stream(self.stream)
+            z.record_stream(self.stream)
+            f.y, f.z = y.data_ptr(), z.data_ptr()
+            f.flags = TPC_IN_DEVICE
+        self._inputs = (y, z, row_offsets, z_lo, z_hi)   # borrowed until the request completes
+        rid = C.c_uint64()
+        _check(load().tpc_track_timeframe(self._h, C.byref(f), C.byref(rid)))
+        return rid.value
+
+    def get(self, rid, blocking=True):
+        t = _Tracks()
+        st = load().tpc_get_tracks(self._h, rid, 1 if blocking else 0, C.byref(t))
+        if st == TPC_E_NOTREADY:
+            return None
+        _check(st)
+        n, nc = t.n_tracks, t.n_track_clusters
+
+        def arr(ptr, count, dt):
+            if count == 0:
+                return np.zeros(0, dt)
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=True)
+
+        return Tracks(n_tracklets=t.n_tracklets, error_flags=t.error_flags,
+                      sector=arr(t.track_sector, n, np.uint32), start=arr(t.track_start, n, np.uint32),
+                      first=arr(t.track_first, n + 1, np.uint32), cluster_ids=arr(t.cluster_ids, nc, np.uint32),
+                      x_ref=arr(t.x_ref, n, np.float32), param=arr(t.param, 5 * n, np.float32).reshape(n, 5),
+                      cov=arr(t.cov, 15 * n, np.float32).reshape(n, 15), chi2=arr(t.chi2, n, np.float32),
+                      ndf=arr(t.ndf, n, np.int32))
+
+    def get_counts(self, rid):
+        """Wait for the request; returns dict(n_tracks, n_track_clusters, n_tracklets, n_steps, error_flags)."""
+        t = _Tracks()
+        _check(load().tpc_get_tracks(self._h, rid, 1, C.byref(t)))
+        return dict(n_tracks=t.n_tracks, n_track_clusters=t.n_track_clusters, n_tracklets=t.n_tracklets,
+                    n_steps=t.n_steps, error_flags=t.error_flags)
+
+    def release(self, rid):
+        _check(load().tpc_release(self._h, rid))
+        self._inputs = None
+
+    def track(self, y, z, row_offsets, z_lo, z_hi, *, host=False):
+        rid = self.submit(y, z, row_offsets, z_lo, z_hi, host=host)
+        try:
+            return self.get(rid)
+        finally:
+            self.release(rid)
+
+    def track_event(self, ev, host=False):
+        if host:
+            return self.track(ev.y, ev.z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi, host=True)
+        torch = self._torch
+        y = torch.from_numpy(ev.y).to(self.device)
+        z = torch.from_numpy(ev.z).to(self.device)
+        return self.track(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+
+    # ---- introspection ----
+    def debug(self, what, dtype):
+        L = load()
+        n = C.c_uint64()
+        _check(L.tpc_debug_copy(self._h, what, None, 0, C.byref(n)))
+        out = np.empty(n.value // np.dtype(dtype).itemsize, dtype)
+        if n.value:
+            _check(L.tpc_debug_copy(self._h, what, out.ctypes.data, n.value, C.byref(n)))
+        return out
+
+    def set_timing(self, on=True):
+        _check(load().tpc_set_timing(self._h, 1 if on else 0))
+
+    def pass_times(self):
+        ms = (C.c_float * N_PASSES)()
+        _check(load().tpc_get_pass_times(self._h, ms, N_PASSES))
+        return dict(zip(PASS_NAMES, [float(v) for v in ms]))

@@ -1,0 +1,194 @@
+"""GPU-vs-oracle comparison helpers for the parity tests.
+
+Tolerances (stated in the tests that use them):
+* C1-C4 (grid order, bin starts, dims, links, starts): bit-exact.
+* C5/C6 (FP32 Kalman filter on the GPU vs FP64 oracle):
+  - assignment agreement >= 99.9% over clusters labelled by either side
+    (label = start position of the owning track);
+  - parameters of tracks found by both sides with the same clusters:
+    >= 99% within |dp_i| <= 1e-4 * max(|p_i|, f_i), f = (1 cm, 1 cm, 1e-2,
+    1e-2, 1e-2 /GeV), and every track within that bound or 0.5 sigma_i
+    (sigma from the oracle covariance);
+  - covariance diagonal: >= 99% within 1e-2 relative, all within 0.1.  The
+    float32 Joseph-form recursion carries a relative error of about
+    eps32 * (prior variance / final variance) = 6e-8 * (25 / 5e-4) = 3e-3 for
+    typical tracks, reaching a few 1e-2 for the shortest low-pT fits;
+  - every GPU covariance SPD.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+FLOORS = np.array([1.0, 1.0, 1e-2, 1e-2, 1e-2])
+PARAM_RTOL = 1e-4
+PARAM_SIGMA_CAP = 0.5
+COV_RTOL = 1e-2
+COV_RTOL_MAX = 0.1
+MIN_AGREEMENT = 0.999
+MIN_FRAC_WITHIN = 0.99
+
+
+def gpu_run(tr, ev, dbg=True, tracklets=True):
+    from paper_2502_09138_amd import tracker as T
+    res = {"tracks": tr.track_event(ev)}
+    if dbg:
+        res["sorted_id"] = tr.debug(T.TPC_DBG_SORTED_ID, np.uint32)
+        res["bin_start"] = tr.debug(T.TPC_DBG_BIN_START, np.uint32)
+        res["row_dims"] = tr.debug(T.TPC_DBG_ROW_DIMS, np.uint32)
+        for k, w in (("up0", T.TPC_DBG_UP0), ("down0", T.TPC_DBG_DOWN0), ("up1", T.TPC_DBG_UP1),
+                     ("down1", T.TPC_DBG_DOWN1)):
+            res[k] = tr.debug(w, np.int32)
+        res["starts"] = tr.debug(T.TPC_DBG_STARTS, np.uint32)
+    if dbg and tracklets:
+        rowhit = tr.debug(T.TPC_DBG_TK_ROWHIT, np.int32)
+        tcap = len(rowhit) // tr.R
+        res["tcap"] = tcap
+        res["tk_rowhit"] = rowhit.reshape(tr.R, tcap)
+        res["tk_info"] = tr.debug(T.TPC_DBG_TK_INFO, np.int32).reshape(4, tcap)
+        res["tk_param"] = tr.debug(T.TPC_DBG_TK_PARAM, np.float32).reshape(5, tcap)
+        res["tk_cov"] = tr.debug(T.TPC_DBG_TK_COV, np.float32).reshape(15, tcap)
+    return res
+
+
+def _shift(a, base):
+    a = a.astype(np.int64)
+    return np.where(a >= 0, a - base, -1)
+
+
+def compare_c1_c4(g, o, R, base=0, n=None, sr0=0, n_sr=None):
+    """Bit-exact comparison of steps C1-C4 on clusters [base, base+n) and rows [sr0, sr0+n_sr)."""
+    n = len(o["sorted_id"]) if n is None else n
+    n_sr = len(o["row_dims"]) if n_sr is None else n_sr
+    assert np.array_equal(g["sorted_id"][base:base + n].astype(np.int64) - base, o["sorted_id"]), "C1 order"
+    assert np.array_equal(g["row_dims"][sr0:sr0 + n_sr], o["row_dims"]), "C1 dims"
+    # bin starts: nb+1 used entries per row at row_offset + 2*sr
+    dims = o["row_dims"]
+    nb = (dims & 0xFFFF).astype(np.int64) * (dims >> 16).astype(np.int64)
+    offs_o = o["_row_offsets"].astype(np.int64)
+    for k in range(n_sr):
+        bo = offs_o[k] + 2 * k
+        bg = base + offs_o[k] + 2 * (sr0 + k)
+        seg_o = o["bin_start"][bo:bo + nb[k] + 1].astype(np.int64)
+        seg_g = g["bin_start"][bg:bg + nb[k] + 1].astype(np.int64) - base
+        if not np.array_equal(seg_o, seg_g):
+            raise AssertionError(f"C1 bin starts differ in row {k}")
+    for key in ("up0", "down0", "up1", "down1"):
+        assert np.array_equal(_shift(g[key][base:base + n], base), o[key]), key
+    gs = g["starts"].astype(np.int64)
+    gs = gs[(gs >= base) & (gs < base + n)] - base
+    assert np.array_equal(gs, o["starts"].astype(np.int64)), "C4 starts"
+
+
+def tracklet_stats(g, o, R, base=0, sample=None):
+    """Compare C5 tracklets start by start; returns a dict of agreement statistics."""
+    gs = g["starts"].astype(np.int64)
+    idx_g = np.nonzero((gs >= base) & (gs < base + len(o["sorted_id"])))[0]
+    which = np.arange(len(o["starts"])) if sample is None else np.asarray(sample)
+    same_hits = 0
+    n_cmp = 0
+    worst = 0.0
+    bad_param = far_param = 0
+    for i_o in which:
+        nh_o = int(o["tk_nhits"][i_o])
+        if nh_o == 0:
+            continue
+        i_g = idx_g[i_o]
+        nh_g = int(g["tk_info"][0, i_g])
+        n_cmp += 1
+        if nh_o < 0 or nh_g < 0:
+            same_hits += int(nh_o == nh_g)
+            continue
+        rin, rout = int(g["tk_info"][1, i_g]), int(g["tk_info"][2, i_g])
+        col = np.full(R, -1, np.int64)
+        col[rin:rout + 1] = g["tk_rowhit"][rin:rout + 1, i_g]
+        col = _shift(col, base)
+        if not np.array_equal(col, o["tk_rowhit"][i_o]):
+            continue
+        same_hits += 1
+        pg = g["tk_param"][:, i_g].astype(np.float64)
+        po = o["tk_param"][i_o]
+        dp = np.abs(pg - po)
+        r = np.max(dp / (PARAM_RTOL * np.maximum(np.abs(po), FLOORS)))
+        worst = max(worst, r)
+        bad_param += int(r > 1.0)
+        sd = np.sqrt(np.diag(unpack_cov(o["tk_cov"][i_o])))
+        far_param += int(r > 1.0 and np.any(dp > PARAM_SIGMA_CAP * sd))
+    return dict(n=n_cmp, same_hits=same_hits, frac_same=same_hits / max(1, n_cmp), worst_param_ratio=float(worst),
+                bad_param=bad_param, far_param=far_param)
+
+
+def labels_gpu(tracks, n_total, base=0, n=None):
+    lab = np.full(n_total, -1, np.int64)
+    for t in range(tracks.n_tracks):
+        lab[tracks.cluster_ids[tracks.first[t]:tracks.first[t + 1]]] = tracks.start[t]
+    n = n_total - base if n is None else n
+    return _shift(lab[base:base + n], base)
+
+
+def labels_oracle(o, n):
+    lab = np.full(n, -1, np.int64)
+    st = o["starts"].astype(np.int64)
+    for t, i in enumerate(o["trk_tracklet"]):
+        lab[o["trk_clusters"][o["trk_first"][t]:o["trk_first"][t + 1]]] = st[i]
+    return lab
+
+
+def unpack_cov(c15):
+    M = np.zeros((5, 5))
+    k = 0
+    for i in range(5):
+        for j in range(i + 1):
+            M[i, j] = M[j, i] = c15[k]
+            k += 1
+    return M
+
+
+def compare_tracks(tracks, o, n_total, base=0):
+    """Track-level parity: assignment agreement, parameters, covariance, SPD."""
+    n = len(o["sorted_id"])
+    lg = labels_gpu(tracks, n_total, base, n)
+    lo = labels_oracle(o, n)
+    either = (lg >= 0) | (lo >= 0)
+    agree = float(np.mean(lg[either] == lo[either])) if either.any() else 1.0
+    # tracks in both with identical clusters
+    st_o = o["starts"].astype(np.int64)
+    o_by_start = {}
+    for t, i in enumerate(o["trk_tracklet"]):
+        o_by_start[int(st_o[i])] = (t, int(i))
+    n_both = n_same = bad_p = bad_c = far_p = far_c = 0
+    worst = 0.0
+    worst_c = 0.0
+    n_spd_fail = 0
+    for t in range(tracks.n_tracks):
+        s = int(tracks.start[t]) - base
+        if s < 0 or s >= n:
+            continue
+        try:
+            np.linalg.cholesky(unpack_cov(tracks.cov[t].astype(np.float64)))
+        except np.linalg.LinAlgError:
+            n_spd_fail += 1
+        if s not in o_by_start:
+            continue
+        n_both += 1
+        to, io = o_by_start[s]
+        cg = np.sort(tracks.cluster_ids[tracks.first[t]:tracks.first[t + 1]].astype(np.int64) - base)
+        co = np.sort(o["trk_clusters"][o["trk_first"][to]:o["trk_first"][to + 1]].astype(np.int64))
+        if not np.array_equal(cg, co):
+            continue
+        n_same += 1
+        po = o["tk_param"][io]
+        dp = np.abs(tracks.param[t].astype(np.float64) - po)
+        r = np.max(dp / (PARAM_RTOL * np.maximum(np.abs(po), FLOORS)))
+        worst = max(worst, r)
+        bad_p += int(r > 1.0)
+        do = np.diag(unpack_cov(o["tk_cov"][io]))
+        far_p += int(r > 1.0 and np.any(dp > PARAM_SIGMA_CAP * np.sqrt(do)))
+        dg = np.diag(unpack_cov(tracks.cov[t].astype(np.float64)))
+        rc = np.max(np.abs(dg - do) / np.abs(do))
+        worst_c = max(worst_c, rc)
+        bad_c += int(rc > COV_RTOL)
+        far_c += int(rc > COV_RTOL_MAX)
+    return dict(agreement=agree, n_labelled=int(either.sum()), n_tracks_gpu=int(tracks.n_tracks),
+                n_tracks_oracle=len(o["trk_tracklet"]), n_both=n_both, n_same=n_same, bad_param=bad_p,
+                far_param=far_p, worst_param_ratio=float(worst), bad_cov=bad_c, far_cov=far_c,
+                worst_cov_rel=float(worst_c), spd_fail=n_spd_fail)

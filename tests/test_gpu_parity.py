@@ -1,0 +1,200 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (derivation in tests/parity.py): C1-C4 bit-exact; >= 99.9% cluster-to-
+track assignment agreement; >= 99% of common tracks with parameters within
+1e-4 relative (with floors) and all within that or 0.5 sigma; covariance
+diagonals >= 99% within 1e-2 relative and all within 0.1; every GPU
+covariance SPD.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2502_09138_amd import synth
+from paper_2502_09138_amd.config import default_config
+
+import parity
+
+pytestmark = pytest.mark.gpu
+R = synth.N_ROWS
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _tracker(ev, **kw):
+    from paper_2502_09138_amd.tracker import Tracker
+    kw.setdefault("max_clusters", max(1, ev.n_clusters))
+    kw.setdefault("max_sectors", ev.n_sectors)
+    return Tracker(default_config(), **kw)
+
+
+def _oracle(ev, construct=True):
+    run = oracle.Run.from_event(default_config().as_dict(), ev).grid().links().starts()
+    if construct:
+        run.construct().select()
+    o = run.result()
+    o["_row_offsets"] = ev.row_offsets
+    return o
+
+
+def _check_tracks(st, label):
+    print(label, st, flush=True)
+    assert st["agreement"] >= parity.MIN_AGREEMENT, st
+    assert st["spd_fail"] == 0, st
+    assert st["n_same"] >= 0.98 * st["n_both"], st
+    assert st["bad_param"] <= (1 - parity.MIN_FRAC_WITHIN) * max(1, st["n_same"]), st
+    assert st["far_param"] == 0, st
+    assert st["bad_cov"] <= (1 - parity.MIN_FRAC_WITHIN) * max(1, st["n_same"]), st
+    assert st["far_cov"] == 0, st
+
+
+def _check_tracklets(ts, label):
+    print(label, "tracklets", ts, flush=True)
+    assert ts["frac_same"] >= 0.99, ts
+    assert ts["bad_param"] <= (1 - parity.MIN_FRAC_WITHIN) * max(1, ts["same_hits"]), ts
+    assert ts["far_param"] == 0, ts
+
+
+def test_single_sector_full_parity(torch_cuda):
+    ev = synth.single_sector(seed=1)
+    print("case: single_sector seed=1 N=", ev.n_clusters, flush=True)
+    tr = _tracker(ev)
+    g = parity.gpu_run(tr, ev)
+    o = _oracle(ev)
+    parity.compare_c1_c4(g, o, R)
+    _check_tracklets(parity.tracklet_stats(g, o, R), "single_sector")
+    _check_tracks(parity.compare_tracks(g["tracks"], o, ev.n_clusters), "single_sector")
+
+
+def test_central_event_sectors(torch_cuda):
+    ev = synth.central_event(seed=2)
+    print("case: central_event seed=2 N=", ev.n_clusters, flush=True)
+    tr = _tracker(ev)
+    g = parity.gpu_run(tr, ev)
+    for s in (0, 9, 18, 35):
+        sub = ev.sector_slice([s])
+        o = _oracle(sub)
+        base = int(ev.row_offsets[s * R])
+        parity.compare_c1_c4(g, o, R, base=base, sr0=s * R, n_sr=R)
+        _check_tracklets(parity.tracklet_stats(g, o, R, base=base), f"sector {s}")
+        _check_tracks(parity.compare_tracks(g["tracks"], o, ev.n_clusters, base=base), f"sector {s}")
+
+
+def test_uneven_chunks_extremes(torch_cuda):
+    ev = synth.uneven_chunks(chunks=range(24))
+    counts = np.diff(ev.row_offsets[::R].astype(np.int64))
+    print("case: uneven_chunks 0..23 N=", ev.n_clusters, "min/max chunk", counts.min(), counts.max(), flush=True)
+    tr = _tracker(ev)
+    g = parity.gpu_run(tr, ev)
+    for s in (int(np.argmin(counts)), int(np.argmax(counts))):
+        sub = ev.sector_slice([s])
+        o = _oracle(sub)
+        base = int(ev.row_offsets[s * R])
+        parity.compare_c1_c4(g, o, R, base=base, sr0=s * R, n_sr=R)
+        _check_tracklets(parity.tracklet_stats(g, o, R, base=base), f"chunk {s}")
+        _check_tracks(parity.compare_tracks(g["tracks"], o, ev.n_clusters, base=base), f"chunk {s}")
+
+
+def test_time_frame_full_size(torch_cuda):
+    """32-orbit frame (~10M clusters): C1-C4 bit-exact everywhere, full C5-C7
+    parity on two sectors, output invariants everywhere."""
+    ev = synth.time_frame(seed=3)
+    print("case: time_frame seed=3 N=", ev.n_clusters, flush=True)
+    tr = _tracker(ev, max_tracklets=ev.n_clusters // 8)
+    g = parity.gpu_run(tr, ev, tracklets=False)
+    o = _oracle(ev, construct=False)
+    parity.compare_c1_c4(g, o, R)
+    print("C1-C4 bit-exact on", ev.n_clusters, "clusters", flush=True)
+    t = g["tracks"]
+    cl = t.cluster_ids
+    assert len(np.unique(cl)) == len(cl)
+    assert np.all(np.diff(t.start.astype(np.int64)) > 0)
+    assert np.array_equal(t.sector, np.searchsorted(ev.row_offsets[::R][1:], t.start, side="right"))
+    for k in range(t.n_tracks):
+        np.linalg.cholesky(parity.unpack_cov(t.cov[k].astype(np.float64)))
+    for s in (5, 30):
+        sub = ev.sector_slice([s])
+        os_ = _oracle(sub)
+        base = int(ev.row_offsets[s * R])
+        _check_tracks(parity.compare_tracks(t, os_, ev.n_clusters, base=base), f"time_frame sector {s}")
+
+
+def test_determinism_and_host_input(torch_cuda):
+    ev = synth.single_sector(seed=4)
+    tr = _tracker(ev)
+    a = tr.track_event(ev)
+    b = tr.track_event(ev)
+    c = tr.track_event(ev, host=True)
+    for x in (b, c):
+        for f in ("sector", "start", "first", "cluster_ids", "x_ref", "param", "cov", "chi2", "ndf"):
+            assert np.array_equal(getattr(a, f), getattr(x, f)), f
+
+
+def test_golden_straight_line_on_gpu(torch_cuda):
+    import json, os
+    from paper_2502_09138_amd.tracker import Tracker
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "straight_line_5rows.json")))
+    cfg = default_config(row_x=np.array(g["row_x"]), row_half_y=np.array(g["row_half_y"]), **g["cuts"])
+    hits = [h for row in g["hits_by_row"] for h in row]
+    offs = np.concatenate([[0], np.cumsum([len(r) for r in g["hits_by_row"]])]).astype(np.uint32)
+    y = np.array([h[0] for h in hits], np.float32)
+    z = np.array([h[1] for h in hits], np.float32)
+    tr = Tracker(cfg, max_clusters=len(hits), max_sectors=1)
+    out = tr.track(y, z, offs, [g["z_lo"]], [g["z_hi"]], host=True)
+    e = g["expect"]
+    assert out.n_tracklets == e["n_starts"] and out.n_tracks == e["n_tracks"]
+    assert sorted(out.cluster_ids.tolist()) == e["track_input_ids"]
+    assert out.x_ref[0] == e["x_ref"]
+    assert np.allclose(out.param[0], e["param"], rtol=0, atol=2e-5)
+
+
+def test_edge_cases(torch_cuda):
+    from paper_2502_09138_amd.tracker import Tracker, TrackerError, TPC_E_INPUT, TPC_E_CAPACITY, TPC_E_BUSY, TPC_E_INVAL
+    cfg = default_config()
+    tr = Tracker(cfg, max_clusters=40000, max_sectors=4, max_tracklets=5000)
+    lo, hi = np.zeros(4, np.float32), np.full(4, 250.0, np.float32)
+    # empty frame
+    out = tr.track(np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(4 * R + 1, np.uint32), lo, hi, host=True)
+    assert out.n_tracks == 0 and out.n_tracklets == 0
+    # one hit per row in sector 1 only, and a row whose hits all share one point (one bin)
+    offs = np.zeros(4 * R + 1, np.uint32)
+    counts = np.zeros(4 * R, np.int64)
+    counts[R:2 * R] = 1
+    counts[2 * R + 50] = 300
+    offs[1:] = np.cumsum(counts)
+    n = int(offs[-1])
+    y = np.zeros(n, np.float32)
+    z = np.full(n, 100.0, np.float32)
+    out = tr.track(y, z, offs, lo, hi, host=True)
+    o = oracle.Run(cfg.as_dict(), offs, y, z, lo, hi).run_all().result()
+    assert out.n_tracks == len(o["trk_tracklet"])
+    assert np.array_equal(np.sort(out.cluster_ids), np.sort(o["trk_clusters"]))
+    # non-finite input -> TPC_E_INPUT
+    y2 = y.copy()
+    y2[3] = np.nan
+    with pytest.raises(TrackerError) as ex:
+        tr.track(y2, z, offs, lo, hi, host=True)
+    assert ex.value.status == TPC_E_INPUT
+    # capacity
+    ev = synth.single_sector(seed=2)
+    small = Tracker(cfg, max_clusters=ev.n_clusters, max_sectors=1, max_tracklets=50)
+    with pytest.raises(TrackerError) as ex:
+        small.track_event(ev)
+    assert ex.value.status == TPC_E_CAPACITY
+    # busy, bad offsets
+    rid = tr.submit(y, z, offs, lo, hi, host=True)
+    with pytest.raises(TrackerError) as ex:
+        tr.submit(y, z, offs, lo, hi, host=True)
+    assert ex.value.status == TPC_E_BUSY
+    tr.release(rid)
+    bad = offs.copy()
+    bad[10] = bad[11] + 1
+    with pytest.raises(TrackerError) as ex:
+        tr.submit(y, z, bad, lo, hi, host=True)
+    assert ex.value.status == TPC_E_INVAL
