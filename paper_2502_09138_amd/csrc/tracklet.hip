@@ -203,10 +203,22 @@ __device__ __forceinline__ bool seed3(float x0, float2 h0, float xm, float2 hm, 
   return cp > 0.0f && fabsf(sp) < k.s_max;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8),
+// each with its own L2.  Tracklets are ordered by sector, so each XCD is given
+// one contiguous eighth of the tracklets: its lanes then search the row grids
+// of a few sectors only, which stay resident in that XCD's L2.
+constexpr uint32_t kXcds = 8;
+
 __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
   const uint32_t nt = min(d.hdr->n_starts, d.tcap);
   const uint32_t R = d.R, T = d.tcap;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
+  const uint32_t need = (nt + kThreads - 1) / kThreads;            // blocks with work
+  const uint32_t per_xcd = (need + kXcds - 1) / kXcds;
+  const uint32_t xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const uint32_t slots = gridDim.x / kXcds;                        // grid is a multiple of kXcds
+  for (uint32_t vb = xcd * per_xcd + slot, end = min(need, (xcd + 1) * per_xcd); vb < end; vb += slots) {
+    const uint32_t i = vb * kThreads + threadIdx.x;
+    if (i >= nt) continue;
     const uint32_t sr0 = d.start_sr[i];
     const uint32_t sec = sr0 / R, r0 = sr0 % R, srb = sec * R;
     const SectorConst sc = d.secs[sec];
@@ -329,6 +341,7 @@ void launch_tracklets(const DevPtrs& d, const KfConst& k, hipStream_t s) {
   if (d.tcap == 0) return;
   uint32_t blocks = (d.tcap + kThreads - 1) / kThreads;
   if (blocks > 16384) blocks = 16384;
+  blocks = (blocks + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(kThreads), 0, s, d, k);
 }
 
