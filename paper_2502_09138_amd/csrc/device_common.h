@@ -92,4 +92,21 @@ __device__ __forceinline__ void block_scan_array(uint32_t* arr, uint32_t n, uint
   __syncthreads();
 }
 
+// XCD-aware grid-stride schedule over n items.  Workgroups are dispatched
+// round-robin over the 8 XCDs (block b -> XCD b % 8), each with its own L2; this
+// gives XCD x the contiguous virtual blocks [x*per, (x+1)*per), so items that
+// share data (tracklets of one sector) are served from one L2.  The grid must be
+// a multiple of kXcds.  Usage: for (uint32_t vb = s.first; vb < s.end; vb += s.stride)
+constexpr uint32_t kXcds = 8;
+struct XcdSched {
+  uint32_t first, end, stride;
+};
+__device__ __forceinline__ XcdSched xcd_sched(uint32_t n_items) {
+  const uint32_t need = (n_items + blockDim.x - 1) / blockDim.x;
+  const uint32_t per = (need + kXcds - 1) / kXcds;
+  const uint32_t xcd = blockIdx.x % kXcds;
+  return XcdSched{xcd * per + blockIdx.x / kXcds, min(need, (xcd + 1) * per), gridDim.x / kXcds};
+}
+inline uint32_t xcd_grid(uint32_t blocks) { return (blocks + kXcds - 1) / kXcds * kXcds; }
+
 }  // namespace tpc

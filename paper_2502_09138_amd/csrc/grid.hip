@@ -36,7 +36,10 @@ __device__ void grid_row(const DevPtrs& d, uint32_t sr, const RowArrays& A, uint
   int ny, nz;
   grid_dims(n, grid_k, rc.ly, sc.lz, ny, nz);
   const uint32_t nb = (uint32_t)(ny * nz);
-  if (threadIdx.x == 0) d.row_dims[sr] = (uint32_t)ny | ((uint32_t)nz << 16);
+  if (threadIdx.x == 0) {
+    d.row_dims[sr] = (uint32_t)ny | ((uint32_t)nz << 16);
+    d.row_meta[sr] = make_uint2(bin_base(d, sr), (uint32_t)ny | ((uint32_t)nz << 16));
+  }
   for (uint32_t b = threadIdx.x; b <= nb; b += blockDim.x) A.cnt[b] = 0;
   __syncthreads();
   bool bad = false;

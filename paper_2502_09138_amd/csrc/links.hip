@@ -61,8 +61,12 @@ __device__ __forceinline__ void stage(RowView& v, uint32_t n, float2* lyz, uint3
   v.bs = lbs;
 }
 
+// Candidate slots per thread for the passing hits of row r+1 (mean 1.6, max 7
+// on a central event); a hit with more falls back to rescanning the window.
+constexpr int kUpSlots = 8;
+
 __device__ __forceinline__ void links_row(const DevPtrs& d, uint32_t sr, const RowView& dn, const RowView& up,
-                                          const RowConst& rc, float rho) {
+                                          const RowConst& rc, float rho, uint16_t* slots) {
 #pragma clang fp contract(off)
   const uint32_t a = d.row_off[sr], n = d.row_off[sr + 1] - a;
   const float t = rc.t;
@@ -70,25 +74,45 @@ __device__ __forceinline__ void links_row(const DevPtrs& d, uint32_t sr, const R
     const float2 h = d.syz[a + j];
     int32_t bu = -1, bd = -1;
     float best = 0.0f;
+    // passing candidates of row r+1, collected once
+    int nu = 0;
+    for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu) {
+      const float2 pu = up.yz[qu];
+      if (!(fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up)) return;
+      if (nu < kUpSlots) slots[nu] = (uint16_t)qu;
+      ++nu;
+    });
+    if (nu == 0) {
+      d.up0[a + j] = -1;
+      d.down0[a + j] = -1;
+      continue;
+    }
+    auto pair = [&](const float2 pd, int32_t gd, uint32_t qu) {
+      const float2 pu = up.yz[qu];
+      const float yp = pd.x + t * (pu.x - pd.x);
+      const float zp = pd.y + t * (pu.y - pd.y);
+      const float ey = h.x - yp, ez = h.y - zp;
+      const float dev = ey * ey + rho * (ez * ez);
+      if (!(dev <= rc.dmax)) return;
+      const int32_t gu = (int32_t)(up.off + qu);
+      if (bu < 0 || dev < best || (dev == best && (gu < bu || (gu == bu && gd < bd)))) {
+        best = dev;
+        bu = gu;
+        bd = gd;
+      }
+    };
     for_window(dn, h.x, h.y, rc.wy_dn, rc.wz_dn, [&](uint32_t qd) {
       const float2 pd = dn.yz[qd];
       if (!(fabsf(pd.x - h.x) <= rc.wy_dn && fabsf(pd.y - h.y) <= rc.wz_dn)) return;
       const int32_t gd = (int32_t)(dn.off + qd);
-      for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu) {
-        const float2 pu = up.yz[qu];
-        if (!(fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up)) return;
-        const float yp = pd.x + t * (pu.x - pd.x);
-        const float zp = pd.y + t * (pu.y - pd.y);
-        const float ey = h.x - yp, ez = h.y - zp;
-        const float dev = ey * ey + rho * (ez * ez);
-        if (!(dev <= rc.dmax)) return;
-        const int32_t gu = (int32_t)(up.off + qu);
-        if (bu < 0 || dev < best || (dev == best && (gu < bu || (gu == bu && gd < bd)))) {
-          best = dev;
-          bu = gu;
-          bd = gd;
-        }
-      });
+      if (nu <= kUpSlots) {
+        for (int k = 0; k < nu; ++k) pair(pd, gd, slots[k]);
+      } else {
+        for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu) {
+          const float2 pu = up.yz[qu];
+          if (fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up) pair(pd, gd, qu);
+        });
+      }
     });
     d.up0[a + j] = bu;
     d.down0[a + j] = bd;
@@ -97,6 +121,7 @@ __device__ __forceinline__ void links_row(const DevPtrs& d, uint32_t sr, const R
 
 __global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, uint32_t cap, float rho) {
   extern __shared__ uint32_t lds[];
+  __shared__ uint16_t slots[kThreads][kUpSlots];
   const uint32_t sr = blockIdx.x;
   const uint32_t R = d.R;
   const uint32_t row = sr % R;
@@ -119,7 +144,7 @@ __global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, uint32_t cap, flo
   if (nd <= cap) stage(dn, nd, lyz, lbs);
   if (nu <= cap) stage(up, nu, lyz + cap, lbs + cap + 2);
   __syncthreads();
-  links_row(d, sr, dn, up, d.rows[row], rho);
+  links_row(d, sr, dn, up, d.rows[row], rho, slots[threadIdx.x]);
 }
 
 }  // namespace

@@ -59,6 +59,7 @@ struct DevPtrs {
   const SectorConst* secs;   // [S]
   // C1
   uint32_t* row_dims;        // [SR]
+  uint2* row_meta;           // [SR] (bin_start offset of the row, dims) for one-load grid lookups
   uint32_t* bin_start;       // [N + 2SR]
   float2* syz;               // [N]
   uint32_t* sid;             // [N]

@@ -40,7 +40,7 @@ constexpr double kCB = 0.00299792458;
 constexpr uint64_t kAlign = 256;
 
 struct Layout {   // byte offsets of every workspace buffer
-  uint64_t row_off, rows, secs, row_dims, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
+  uint64_t row_off, rows, secs, row_dims, row_meta, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
       row_start_off, start_pos, start_sr, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, W, tk_pack, tk_scan,
       out_sector, out_start, out_first, out_clusters, out_xref, out_param, out_cov, out_chi2, out_ndf, scan_blocks,
       hdr, in_y, in_z, total;
@@ -75,6 +75,7 @@ Layout layout_of(const Caps& k) {
   L.rows = take((uint64_t)k.R * sizeof(RowConst));
   L.secs = take((uint64_t)k.Smax * sizeof(SectorConst));
   L.row_dims = take(k.SRmax * 4);
+  L.row_meta = take(k.SRmax * 8);
   L.bin_start = take((k.N + 2 * k.SRmax + 2) * 4);
   L.syz = take(k.N * 8);
   L.sid = take(k.N * 4);
@@ -300,6 +301,7 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   d.rows = (const RowConst*)(w + lay.rows);
   d.secs = (const SectorConst*)(w + lay.secs);
   d.row_dims = (uint32_t*)(w + lay.row_dims);
+  d.row_meta = (uint2*)(w + lay.row_meta);
   d.bin_start = (uint32_t*)(w + lay.bin_start);
   d.syz = (float2*)(w + lay.syz);
   d.sid = (uint32_t*)(w + lay.sid);
@@ -532,6 +534,38 @@ tpc_status tpc_get_tracks(tpc_tracker* t, uint64_t request_id, int32_t blocking,
   out->cov = (const float*)host(L.out_cov);
   out->chi2 = (const float*)host(L.out_chi2);
   out->ndf = (const int32_t*)host(L.out_ndf);
+  return TPC_OK;
+}
+
+tpc_status tpc_get_tracks_device(tpc_tracker* t, uint64_t request_id, int32_t blocking, tpc_tracks* out) {
+  if (!t || !out) return fail(TPC_E_INVAL, "NULL argument");
+  if (!t->in_flight || request_id != t->cur_id) return fail(TPC_E_INVAL, "unknown request id");
+  HIP_TRY(hipSetDevice(t->device));
+  if (!blocking) {
+    hipError_t q = hipEventQuery(t->done);
+    if (q == hipErrorNotReady) return fail(TPC_E_NOTREADY, "request still running");
+    if (q != hipSuccess) return fail(TPC_E_DEVICE, hipGetErrorString(q));
+  }
+  HIP_TRY(hipEventSynchronize(t->done));
+  std::memset(out, 0, sizeof *out);
+  const ResultHeader h = *t->h_hdr;
+  out->error_flags = h.error_flags;
+  out->n_tracklets = h.n_starts;
+  out->n_steps = h.n_steps;
+  if (h.error_flags & TPC_ERR_NONFINITE) return fail(TPC_E_INPUT, "non-finite or out-of-range cluster coordinate");
+  if (h.error_flags) return fail(TPC_E_CAPACITY, "capacity exceeded (see error_flags)");
+  const DevPtrs& d = t->d;
+  out->n_tracks = h.n_tracks;
+  out->n_track_clusters = h.n_track_clusters;
+  out->track_sector = d.out_sector;
+  out->track_start = d.out_start;
+  out->track_first = d.out_first;
+  out->cluster_ids = d.out_clusters;
+  out->x_ref = d.out_xref;
+  out->param = d.out_param;
+  out->cov = d.out_cov;
+  out->chi2 = d.out_chi2;
+  out->ndf = d.out_ndf;
   return TPC_OK;
 }
 

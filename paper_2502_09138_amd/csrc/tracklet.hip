@@ -2,15 +2,30 @@
 //
 // One lane per tracklet (chain start).  The helix state p[5] and packed
 // covariance C[15] live in float32 registers; the transport exploits the
-// sparsity of the Jacobian (6 non-trivial entries).  The lane walks its chain
-// (dependent up1 gathers), seeds from three chain hits, fits the chain,
-// extends outward through the row grids and refits inward with a fresh
+// sparsity of the Jacobian (6 non-trivial entries) and the update uses the
+// Joseph form, which keeps the float32 covariance positive definite on short,
+// strongly curved fits where the plain C - KHC form does not.  The lane walks
+// its chain (dependent up1 gathers), seeds from three chain hits, fits the
+// chain, extends outward through the row grids and refits inward with a fresh
 // covariance, filling gaps and extending below the chain.
+//
+// Latency is the bound (each row step is a dependent chain: propagate ->
+// grid lookup -> candidate loads -> update), so the per-row constants are
+// staged in LDS, a row's grid is located with one 8-byte load, and the
+// Kalman arithmetic uses the hardware reciprocal / square root (the step is
+// tolerance-checked against the FP64 definition, not bit-exact).
 //
 // The per-tracklet row -> hit column lives in global memory (row-major over
 // tracklets, so lanes at the same row write one coalesced segment); the
 // downward pass rewrites every row in [x_ref row, outermost row] with its
 // final value, which is the only range the selector reads.
+//
+// z precision: in a continuous-readout frame the drift coordinate reaches
+// several thousand cm, where one float32 ulp is ~5e-4 cm; summed over ~150
+// steps that shifts tan(lambda) by ~1e-4 relative.  Each lane therefore keeps
+// the state's z relative to its start hit (zref); z_m - zref is exact in
+// float32 for the hits of one track (Sterbenz), and zref is added back only
+// when the result is stored.
 #include "device_common.h"
 
 namespace tpc {
@@ -19,10 +34,18 @@ namespace {
 constexpr int kThreads = 64;
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }   // i >= j
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 
 struct Trk {
   float p[5];
   float c[15];
+};
+
+// Per-row constants used in the tracklet loop: x, half-width, y_lo, 1/(2Y).
+struct RowK {
+  float x, half_y, y_lo, inv_wy;
 };
 
 // asin(u)/u and d/du of it; |u| is below 0.02 for row-to-row steps.
@@ -35,7 +58,7 @@ __device__ __forceinline__ float asin_over_prime(float u) {
   const float u2 = u * u;
   if (fabsf(u) < 0.1f)
     return u * (1.0f / 3.0f + u2 * (3.0f / 10.0f + u2 * (15.0f / 56.0f + u2 * (35.0f / 144.0f))));
-  return (u / sqrtf(1.0f - u2) - asinf(u)) / u2;
+  return (u * frsqrt(1.0f - u2) - asinf(u)) / u2;
 }
 
 // Helix transport from x to x + dx with covariance; false on |sin phi| >= s_max or |u| >= 1.
@@ -45,22 +68,23 @@ __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
   if (!(fabsf(s1) < k.s_max)) return false;
   const float s2 = s1 + kap * dx;
   if (!(fabsf(s2) < k.s_max)) return false;
-  const float c1 = sqrtf((1.0f - s1) * (1.0f + s1));
-  const float c2 = sqrtf((1.0f - s2) * (1.0f + s2));
-  const float ic = 1.0f / (c1 + c2);
+  const float c1 = fsqrt((1.0f - s1) * (1.0f + s1));
+  const float c2 = fsqrt((1.0f - s2) * (1.0f + s2));
+  const float ic = frcp(c1 + c2);
   const float dy = dx * ((s1 + s2) * ic);
-  const float L = sqrtf(dx * dx + dy * dy);
+  const float L = fsqrt(dx * dx + dy * dy);
   const float u = 0.5f * kap * L;
   if (!(fabsf(u) < 1.0f)) return false;
   const float sgn = dx >= 0.0f ? 1.0f : -1.0f;
   const float S = sgn * L * asin_over(u);
   // Jacobian entries (exact derivative of the map above)
+  const float ic1 = frcp(c1), ic2 = frcp(c2);
   const float D = (1.0f + c1 * c2 + s1 * s2) * (ic * ic);
-  const float ddy_ds1 = dx * D * (1.0f / c1 + 1.0f / c2);
-  const float ddy_dk = dx * dx * (D / c2) * k.bk;
-  const float dS_dL = sgn / sqrtf(1.0f - u * u);
+  const float ddy_ds1 = dx * D * (ic1 + ic2);
+  const float ddy_dk = dx * dx * (D * ic2) * k.bk;
+  const float dS_dL = sgn * frsqrt(1.0f - u * u);
   const float dS_dkap = sgn * 0.5f * L * L * asin_over_prime(u);
-  const float dL_ddy = L > 0.0f ? dy / L : 0.0f;
+  const float dL_ddy = L > 0.0f ? dy * frcp(L) : 0.0f;
   const float A = ddy_ds1;                                // F02
   const float B = ddy_dk;                                 // F04
   const float Cc = tl * dS_dL * dL_ddy * ddy_ds1;         // F12
@@ -99,17 +123,17 @@ __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
   return true;
 }
 
-// Kalman update with a measurement of (y, z).
+// Kalman update with a measurement of (y, z), Joseph form.
 __device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst& k, float& chi2) {
   float* c = t.c;
   const float r0 = ym - t.p[0], r1 = zm - t.p[1];
   const float S00 = c[0] + k.vy, S01 = c[1], S11 = c[2] + k.vz;
-  const float id = 1.0f / (S00 * S11 - S01 * S01);
+  const float id = frcp(S00 * S11 - S01 * S01);
   const float I00 = S11 * id, I01 = -S01 * id, I11 = S00 * id;
-  float c0[5], c1[5];   // rows 0 and 1 of C (C_i0, C_i1)
+  float c0[5], c1[5];   // columns 0 and 1 of C (C_i0, C_i1)
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    c0[i] = i >= 0 ? c[tri(i, 0)] : 0.0f;
+    c0[i] = c[tri(i, 0)];
     c1[i] = i >= 1 ? c[tri(i, 1)] : c[tri(1, 0)];
   }
   float K0[5], K1[5];
@@ -119,8 +143,7 @@ __device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst
     K1[i] = c0[i] * I01 + c1[i] * I11;
     t.p[i] += K0[i] * r0 + K1[i] * r1;
   }
-  // Joseph form: C' = (I - K H) C (I - K H)^T + K V K^T, evaluated on the packed triangle.
-  // P = (I - K H) C; only rows of C enter, and H picks columns 0 and 1.
+  // P = (I - K H) C, then C' = P (I - K H)^T + K V K^T on the lower triangle
   float P[5][5];
 #pragma unroll
   for (int i = 0; i < 5; ++i)
@@ -148,26 +171,27 @@ __device__ __forceinline__ void set_c0(Trk& t, const KfConst& k) {
 }
 
 // Grid search in row sr for the candidate closest to (yp, zp); -1 if none.
-__device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const RowConst& rc, const SectorConst& sc,
-                                          const Trk& t, const KfConst& k) {
+__device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const RowK& rk, const SectorConst& sc,
+                                          const Trk& t, const KfConst& k, float zref) {
+  const uint2 meta = d.row_meta[sr];
   const float sy2 = t.c[0] + k.vy, sz2 = t.c[2] + k.vz;
-  const float wy = fminf(k.gate * sqrtf(sy2), k.cap), wz = fminf(k.gate * sqrtf(sz2), k.cap);
-  const float isy = 1.0f / sy2, isz = 1.0f / sz2;
-  const float yp = t.p[0], zp = t.p[1];
-  const uint32_t dims = d.row_dims[sr];
-  const int ny = (int)(dims & 0xFFFFu), nz = (int)(dims >> 16);
-  const int iy0 = bin1((yp - wy) - kWinPad, rc.y_lo, rc.inv_wy, ny);
-  const int iy1 = bin1((yp + wy) + kWinPad, rc.y_lo, rc.inv_wy, ny);
-  const int iz0 = bin1((zp - wz) - kWinPad, sc.z_lo, sc.inv_wz, nz);
-  const int iz1 = bin1((zp + wz) + kWinPad, sc.z_lo, sc.inv_wz, nz);
-  const uint32_t* bs = d.bin_start + bin_base(d, sr);
+  const float wy = fminf(k.gate * fsqrt(sy2), k.cap), wz = fminf(k.gate * fsqrt(sz2), k.cap);
+  const float isy = frcp(sy2), isz = frcp(sz2);
+  const float yp = t.p[0], zp = t.p[1];          // zp relative to zref
+  const float za = zref + zp;                     // absolute, for the bin range only
+  const int ny = (int)(meta.y & 0xFFFFu), nz = (int)(meta.y >> 16);
+  const int iy0 = bin1((yp - wy) - kWinPad, rk.y_lo, rk.inv_wy, ny);
+  const int iy1 = bin1((yp + wy) + kWinPad, rk.y_lo, rk.inv_wy, ny);
+  const int iz0 = bin1((za - wz) - kWinPad, sc.z_lo, sc.inv_wz, nz);
+  const int iz1 = bin1((za + wz) + kWinPad, sc.z_lo, sc.inv_wz, nz);
+  const uint32_t* bs = d.bin_start + meta.x;
   int32_t best = -1;
   float bd = 0.0f;
   for (int iz = iz0; iz <= iz1; ++iz) {
     const uint32_t lo = bs[iz * ny + iy0], hi = bs[iz * ny + iy1 + 1];
     for (uint32_t q = lo; q < hi; ++q) {
       const float2 h = d.syz[q];
-      const float dy = h.x - yp, dz = h.y - zp;
+      const float dy = h.x - yp, dz = (h.y - zref) - zp;
       if (!(fabsf(dy) <= wy && fabsf(dz) <= wz)) continue;
       const float dd = dy * dy * isy + dz * dz * isz;
       if (best < 0 || dd < bd) {
@@ -196,27 +220,93 @@ __device__ __forceinline__ bool seed3(float x0, float2 h0, float xm, float2 hm, 
   float sp, cp;
   sincosf(phi0, &sp, &cp);
   t.p[0] = h0.x;
-  t.p[1] = h0.y;
+  t.p[1] = 0.0f;             // z relative to the start hit
   t.p[2] = sp;
   t.p[3] = (hl.y - h0.y) / s0l;
   t.p[4] = qpt;
   return cp > 0.0f && fabsf(sp) < k.s_max;
 }
 
+__device__ __forceinline__ void load_rows(const DevPtrs& d, RowK* lrows) {
+  for (uint32_t r = threadIdx.x; r < d.R; r += blockDim.x) {
+    const RowConst rc = d.rows[r];
+    lrows[r] = RowK{rc.x, rc.half_y, rc.y_lo, rc.inv_wy};
+  }
+  __syncthreads();
+}
+
+// SPD guard for the stored covariance.  Near-singular fits (a short, strongly
+// curved arc can correlate sin phi and q/pT at 0.99) sit within float32
+// rounding of the positive-definite boundary; LDL^T with every pivot floored
+// at kPivotFloor * C_kk returns them to a nearby positive-definite matrix and
+// leaves every other covariance untouched (no rebuild when no pivot is low).
+constexpr float kPivotFloor = 1e-5f;
+
+__device__ __forceinline__ void spd_guard(float* c) {
+  float L[5][5], D[5];
+  bool fixed = false;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    float dk = c[tri(k, k)];
+#pragma unroll
+    for (int j = 0; j < k; ++j) dk -= L[k][j] * L[k][j] * D[j];
+    const float floor_k = kPivotFloor * c[tri(k, k)];
+    if (!(dk > floor_k)) {
+      dk = floor_k;
+      fixed = true;
+    }
+    D[k] = dk;
+    const float idk = 1.0f / dk;
+#pragma unroll
+    for (int i = k + 1; i < 5; ++i) {
+      float v = c[tri(i, k)];
+#pragma unroll
+      for (int j = 0; j < k; ++j) v -= L[i][j] * L[k][j] * D[j];
+      L[i][k] = v * idk;
+    }
+  }
+  if (!fixed) return;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      float v = (i == j ? 1.0f : L[i][j]) * D[j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) v += L[i][q] * L[j][q] * D[q];
+      c[tri(i, j)] = v;
+    }
+}
+
+__device__ __forceinline__ void store_tracklet(const DevPtrs& d, uint32_t i, int nh, uint32_t rin, uint32_t rout,
+                                               uint32_t r0, const Trk& snap, float chi2, float zref) {
+  const uint32_t T = d.tcap;
+  d.tk_info[i] = nh;
+  d.tk_info[T + i] = (int32_t)rin;
+  d.tk_info[2 * T + i] = (int32_t)rout;
+  d.tk_info[3 * T + i] = (int32_t)r0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) d.tk_param[(size_t)q * T + i] = q == 1 ? snap.p[q] + zref : snap.p[q];
+  float c[15];
+#pragma unroll
+  for (int q = 0; q < 15; ++q) c[q] = snap.c[q];
+  spd_guard(c);
+#pragma unroll
+  for (int q = 0; q < 15; ++q) d.tk_cov[(size_t)q * T + i] = c[q];
+  d.tk_chi2[i] = chi2;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8),
 // each with its own L2.  Tracklets are ordered by sector, so each XCD is given
 // one contiguous eighth of the tracklets: its lanes then search the row grids
 // of a few sectors only, which stay resident in that XCD's L2.
-constexpr uint32_t kXcds = 8;
-
 __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
+  __shared__ RowK lrows[kMaxRows];
+  load_rows(d, lrows);
   const uint32_t nt = min(d.hdr->n_starts, d.tcap);
   const uint32_t R = d.R, T = d.tcap;
-  const uint32_t need = (nt + kThreads - 1) / kThreads;            // blocks with work
-  const uint32_t per_xcd = (need + kXcds - 1) / kXcds;
-  const uint32_t xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
-  const uint32_t slots = gridDim.x / kXcds;                        // grid is a multiple of kXcds
-  for (uint32_t vb = xcd * per_xcd + slot, end = min(need, (xcd + 1) * per_xcd); vb < end; vb += slots) {
+  const XcdSched sch = xcd_sched(nt);
+  unsigned long long my_steps = 0;
+  for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
     const uint32_t i = vb * kThreads + threadIdx.x;
     if (i >= nt) continue;
     const uint32_t sr0 = d.start_sr[i];
@@ -237,24 +327,25 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
     const int32_t pm = H[(size_t)(r0 + m) * T];
     Trk t;
     const float2 h0 = d.syz[d.start_pos[i]];
-    if (!seed3(d.rows[r0].x, h0, d.rows[r0 + m].x, d.syz[pm], d.rows[rl].x, d.syz[plast], k, t)) {
+    const float zref = h0.y;
+    if (!seed3(lrows[r0].x, h0, lrows[r0 + m].x, d.syz[pm], lrows[rl].x, d.syz[plast], k, t)) {
       d.tk_info[i] = -1;
       continue;
     }
     set_c0(t, k);
     float chi2 = 0.0f;
     bool ok = true;
-    float xprev = d.rows[r0].x;
+    float xprev = lrows[r0].x;
     // chain fit (no gate)
     for (uint32_t r = r0 + 1; r <= rl; ++r) {
-      const float x = d.rows[r].x;
+      const float x = lrows[r].x;
       if (!propagate(t, x - xprev, k)) {
         ok = false;
         break;
       }
       xprev = x;
       const float2 h = d.syz[H[(size_t)r * T]];
-      update(t, h.x, h.y, k, chi2);
+      update(t, h.x, h.y - zref, k, chi2);
     }
     if (!ok) {
       d.tk_info[i] = -2;
@@ -268,16 +359,16 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
     uint32_t rout = rl;
     int miss = 0;
     for (uint32_t r = rl + 1; r < R; ++r) {
-      const RowConst rc = d.rows[r];
+      const RowK rk = lrows[r];
       ++steps;
-      if (!propagate(t, rc.x - xprev, k)) break;
-      xprev = rc.x;
-      if (fabsf(t.p[0]) > rc.half_y + k.margin) break;
-      const int32_t h = search(d, srb + r, rc, sc, t, k);
+      if (!propagate(t, rk.x - xprev, k)) break;
+      xprev = rk.x;
+      if (fabsf(t.p[0]) > rk.half_y + k.margin) break;
+      const int32_t h = search(d, srb + r, rk, sc, t, k, zref);
       H[(size_t)r * T] = h;
       if (h >= 0) {
         const float2 hm = d.syz[h];
-        update(t, hm.x, hm.y, k, chi2);
+        update(t, hm.x, hm.y - zref, k, chi2);
 #pragma unroll
         for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
         rout = r;
@@ -292,28 +383,28 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
 #pragma unroll
       for (int q = 2; q < 5; ++q) t.p[q] = pout[q];
       t.p[0] = ho.x;
-      t.p[1] = ho.y;
+      t.p[1] = ho.y - zref;
     }
     set_c0(t, k);
     chi2 = 0.0f;
     int nh = 1;
     Trk snap = t;
     uint32_t rin = rout;
-    xprev = d.rows[rout].x;
+    xprev = lrows[rout].x;
     miss = 0;
     for (int r = (int)rout - 1; r >= 0; --r) {
-      const RowConst rc = d.rows[r];
+      const RowK rk = lrows[r];
       ++steps;
-      if (!propagate(t, rc.x - xprev, k)) break;
-      xprev = rc.x;
+      if (!propagate(t, rk.x - xprev, k)) break;
+      xprev = rk.x;
       const bool below = (uint32_t)r < r0;
-      if (below && fabsf(t.p[0]) > rc.half_y + k.margin) break;
+      if (below && fabsf(t.p[0]) > rk.half_y + k.margin) break;
       int32_t h = below ? -1 : H[(size_t)r * T];
-      if (h < 0) h = search(d, srb + (uint32_t)r, rc, sc, t, k);
+      if (h < 0) h = search(d, srb + (uint32_t)r, rk, sc, t, k, zref);
       H[(size_t)r * T] = h;
       if (h >= 0) {
         const float2 hm = d.syz[h];
-        update(t, hm.x, hm.y, k, chi2);
+        update(t, hm.x, hm.y - zref, k, chi2);
         ++nh;
         snap = t;
         rin = (uint32_t)r;
@@ -322,17 +413,10 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
         break;
       }
     }
-    d.tk_info[i] = nh;
-    d.tk_info[T + i] = (int32_t)rin;
-    d.tk_info[2 * T + i] = (int32_t)rout;
-    d.tk_info[3 * T + i] = (int32_t)r0;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) d.tk_param[(size_t)q * T + i] = snap.p[q];
-#pragma unroll
-    for (int q = 0; q < 15; ++q) d.tk_cov[(size_t)q * T + i] = snap.c[q];
-    d.tk_chi2[i] = chi2;
-    atomicAdd(&d.hdr->n_steps, (unsigned long long)steps);
+    store_tracklet(d, i, nh, rin, rout, r0, snap, chi2, zref);
+    my_steps += steps;
   }
+  if (my_steps) atomicAdd(&d.hdr->n_steps, my_steps);
 }
 
 }  // namespace
@@ -341,7 +425,7 @@ void launch_tracklets(const DevPtrs& d, const KfConst& k, hipStream_t s) {
   if (d.tcap == 0) return;
   uint32_t blocks = (d.tcap + kThreads - 1) / kThreads;
   if (blocks > 16384) blocks = 16384;
-  blocks = (blocks + kXcds - 1) / kXcds * kXcds;
+  blocks = xcd_grid(blocks);
   hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(kThreads), 0, s, d, k);
 }
 

@@ -74,7 +74,7 @@ class _Tracks(C.Structure):
 
 
 EXPORTED = ("tpc_default_config", "tpc_workspace_bytes", "tpc_tracker_create", "tpc_tracker_destroy",
-            "tpc_track_timeframe", "tpc_get_tracks", "tpc_release", "tpc_last_error", "tpc_debug_copy",
+            "tpc_track_timeframe", "tpc_get_tracks", "tpc_get_tracks_device", "tpc_release", "tpc_last_error", "tpc_debug_copy",
             "tpc_set_timing", "tpc_get_pass_times")
 
 _lib = None
@@ -100,6 +100,8 @@ def load():
     L.tpc_track_timeframe.argtypes = [C.c_void_p, P(_Frame), P(C.c_uint64)]
     L.tpc_get_tracks.restype = C.c_int32
     L.tpc_get_tracks.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, P(_Tracks)]
+    L.tpc_get_tracks_device.restype = C.c_int32
+    L.tpc_get_tracks_device.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, P(_Tracks)]
     L.tpc_release.restype = C.c_int32
     L.tpc_release.argtypes = [C.c_void_p, C.c_uint64]
     L.tpc_last_error.restype = C.c_char_p
@@ -252,6 +254,15 @@ class Tracker:
                       x_ref=arr(t.x_ref, n, np.float32), param=arr(t.param, 5 * n, np.float32).reshape(n, 5),
                       cov=arr(t.cov, 15 * n, np.float32).reshape(n, 15), chi2=arr(t.chi2, n, np.float32),
                       ndf=arr(t.ndf, n, np.int32))
+
+    def get_device(self, rid):
+        """Wait for the request; counts plus device addresses of the output arrays (no copy)."""
+        t = _Tracks()
+        _check(load().tpc_get_tracks_device(self._h, rid, 1, C.byref(t)))
+        addr = lambda p: C.cast(p, C.c_void_p).value or 0
+        return dict(n_tracks=t.n_tracks, n_track_clusters=t.n_track_clusters, n_tracklets=t.n_tracklets,
+                    n_steps=t.n_steps, error_flags=t.error_flags, cluster_ids=addr(t.cluster_ids),
+                    track_first=addr(t.track_first), param=addr(t.param), cov=addr(t.cov))
 
     def get_counts(self, rid):
         """Wait for the request; returns dict(n_tracks, n_track_clusters, n_tracklets, n_steps, error_flags)."""
