@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--workload", default="central_event")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="tracklet kernel schedule: 0 auto, 1 per-lane gathers, 2 row-synchronous LDS stage")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this size first (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -99,7 +101,7 @@ def main():
     y = torch.from_numpy(ev.y).to(dev)
     z = torch.from_numpy(ev.z).to(dev)
     torch.cuda.synchronize()
-    tr = Tracker(default_config(), max_clusters=N, max_sectors=ev.n_sectors)
+    tr = Tracker(default_config(), max_clusters=N, max_sectors=ev.n_sectors, tracklet_schedule=args.schedule)
     tr.set_timing(True)
 
     if args.calib_copy_mb:
@@ -170,7 +172,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": dict(wl, n_clusters=N, n_sectors=ev.n_sectors, n_rows=152, tracklets=counts["n_tracklets"],
-                       tracks=counts["n_tracks"]),
+                       tracks=counts["n_tracks"], tracklet_schedule=args.schedule),
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 4),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 4)},
         "e2e_host_copy": {"value": round(N * n_e2e / e2e, 1), "unit": "clusters/s",

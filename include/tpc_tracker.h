@@ -148,6 +148,10 @@ typedef struct {
   double gate_nsigma, win_cap, edge_margin;    /* search gate g, window cap (cm), edge margin (cm) */
   int32_t max_miss, min_tracklet_hits, min_track_hits;
   double min_owned_frac;
+  /* schedule of the tracklet kernel (results are identical):
+   * 0 = automatic, 1 = one lane per tracklet with per-lane grid gathers,
+   * 2 = row-synchronous waves with the row grid staged in LDS */
+  int32_t tracklet_schedule;
   /* capacities (device workspace is sized from these) */
   uint32_t max_sectors;
   uint64_t max_clusters;           /* < 2^31 */

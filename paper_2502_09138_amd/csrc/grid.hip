@@ -8,7 +8,6 @@
 //   4. each position ranks its id among the (few) ids of its own bin, which
 //      restores input order inside the bin without a global sort.
 // Coordinates are checked for NaN/Inf and |.| > TPC_MAX_COORD on the way.
-// The ownership array W of step C6 is cleared here for the row's positions.
 #include "device_common.h"
 
 namespace tpc {
@@ -66,7 +65,6 @@ __device__ void grid_row(const DevPtrs& d, uint32_t sr, const RowArrays& A, uint
     const uint32_t out = a + b0 + rank;
     d.sid[out] = a + j;
     d.syz[out] = make_float2(d.y[a + j], d.z[a + j]);
-    d.W[a + p] = 0ull;
   }
   __syncthreads();
   // row-local bin starts -> global sorted positions (in place when cnt is the bin_start row itself)

@@ -1,30 +1,177 @@
 // K6: tracklet selector and canonical output -- steps C6 and C7.
 //
-// k_claim: every valid tracklet raises W[hit] to its key with a 64-bit
-//   atomicMax (commutative, so the result does not depend on scheduling).
-// k_own:   counts the hits each tracklet still owns and decides acceptance;
-//   packs (owned << 32) | accepted for one 64-bit scan that yields both the
-//   track index and the cluster offset.
-// k_emit:  writes accepted tracks at their scanned slots (tracklet order =
-//   ascending start position = canonical order).
-// k_finish: track and cluster totals, capacity flags, final offset.
+// Ownership key.  The definition orders tracklets by (nHits, then smaller
+// startPos).  Tracklet index i in the start list is ascending in startPos, so
+// key32 = (nHits << 23) | (2^23 - 1 - i) orders them identically (nHits <= 255,
+// i < 2^23 = the tracklet capacity limit) in 4 bytes instead of 8.
+//
+// Tiled selection (the default).  Every tracklet's hits lie in one sector, and
+// the row -> hit columns are stored row-major over tracklets, so the tracklets
+// of a sector read one row as a contiguous segment.  A workgroup owns a tile =
+// (sector, block of consecutive rows) and keeps the tile's ownership words in
+// LDS:
+//   k_claim_tiles  every valid tracklet of the sector raises W_tile[hit] with an
+//                  LDS atomicMax; the tile is then written to W (coalesced) --
+//                  every position is written, so W needs no clearing;
+//   k_own_tiles    counts each tracklet's owned hits in the tile -> own_part;
+//   k_accept       sums the tiles, applies the acceptance rule, turns own_part
+//                  into per-tile prefixes and packs (owned << 32) | accepted for
+//                  one 64-bit scan giving track index and cluster offset;
+//   k_emit_tiles   writes the owned cluster ids of each accepted tracklet at
+//                  offset + prefix, row by row (ascending row order);
+//   k_records      writes the per-track records (canonical order = tracklet
+//                  order = ascending start position);
+//   k_finish       totals and capacity flags.
+// Rows too large for an LDS tile use the same steps with W in global memory,
+// one thread per tracklet (k_claim_g / k_own_g / k_emit_g).
 #include "device_common.h"
 
 namespace tpc {
 namespace {
 
 constexpr int kThreads = 256;
-
-__device__ __forceinline__ unsigned long long key_of(uint32_t nhits, uint32_t start_pos) {
-  return ((unsigned long long)nhits << 32) | (unsigned long long)(0xFFFFFFFFu - start_pos);
-}
-
-__device__ __forceinline__ uint32_t n_tracklets(const DevPtrs& d) { return min(d.hdr->n_starts, d.tcap); }
-
-// Row loops are unrolled by kUnroll with all loads issued before use, so a
-// lane keeps kUnroll independent gathers in flight instead of one.
 constexpr int kUnroll = 8;
 
+__device__ __forceinline__ uint32_t key32(uint32_t nh, uint32_t i) { return (nh << 23) | (0x7FFFFFu - i); }
+__device__ __forceinline__ uint32_t n_tracklets(const DevPtrs& d) { return min(d.hdr->n_starts, d.tcap); }
+
+struct Tile {
+  uint32_t s, ra, rb, first, n, ts, te;
+};
+
+__device__ __forceinline__ Tile tile_of(const DevPtrs& d, uint32_t tile_rows, uint32_t n_tiles) {
+  Tile t;
+  t.s = blockIdx.x / n_tiles;
+  const uint32_t tt = blockIdx.x % n_tiles;
+  t.ra = tt * tile_rows;
+  t.rb = min(d.R, t.ra + tile_rows);
+  const uint32_t srb = t.s * d.R;
+  t.first = d.row_off[srb + t.ra];
+  t.n = d.row_off[srb + t.rb] - t.first;
+  const uint32_t T = n_tracklets(d);
+  t.ts = min(d.row_start_off[srb], T);
+  t.te = min(d.row_start_off[srb + d.R], T);
+  return t;
+}
+
+__global__ void __launch_bounds__(kThreads) k_claim_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
+  extern __shared__ uint32_t wt[];
+  const Tile tl = tile_of(d, tile_rows, n_tiles);
+  const uint32_t T = d.tcap;
+  for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) wt[j] = 0u;
+  __syncthreads();
+  for (uint32_t i = tl.ts + threadIdx.x; i < tl.te; i += blockDim.x) {
+    const int32_t nh = d.tk_info[i];
+    if (nh < k.min_tracklet_hits) continue;
+    const int32_t a = max((int32_t)tl.ra, d.tk_info[T + i]), b = min((int32_t)tl.rb - 1, d.tk_info[2 * T + i]);
+    const uint32_t key = key32((uint32_t)nh, i);
+    for (int32_t r = a; r <= b; ++r) {
+      const int32_t h = d.tk_rowhit[(size_t)r * T + i];
+      if (h >= 0) atomicMax(&wt[(uint32_t)h - tl.first], key);
+    }
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) d.W[tl.first + j] = wt[j];
+}
+
+__global__ void __launch_bounds__(kThreads) k_own_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
+  extern __shared__ uint32_t wt[];
+  const Tile tl = tile_of(d, tile_rows, n_tiles);
+  const uint32_t T = d.tcap, tt = blockIdx.x % n_tiles;
+  for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) wt[j] = d.W[tl.first + j];
+  __syncthreads();
+  for (uint32_t i = tl.ts + threadIdx.x; i < tl.te; i += blockDim.x) {
+    const int32_t nh = d.tk_info[i];
+    uint32_t cnt = 0;
+    if (nh >= k.min_tracklet_hits) {
+      const int32_t a = max((int32_t)tl.ra, d.tk_info[T + i]), b = min((int32_t)tl.rb - 1, d.tk_info[2 * T + i]);
+      const uint32_t key = key32((uint32_t)nh, i);
+      for (int32_t r = a; r <= b; ++r) {
+        const int32_t h = d.tk_rowhit[(size_t)r * T + i];
+        cnt += (h >= 0 && wt[(uint32_t)h - tl.first] == key) ? 1u : 0u;
+      }
+    }
+    d.own_part[(size_t)tt * T + i] = (uint8_t)cnt;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_accept(DevPtrs d, KfConst k, uint32_t tile_rows) {
+  const uint32_t nt = n_tracklets(d), T = d.tcap;
+  const XcdSched sch = xcd_sched(nt);
+  for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
+    const uint32_t i = vb * blockDim.x + threadIdx.x;
+    if (i >= nt) continue;
+    const int32_t nh = d.tk_info[i];
+    unsigned long long packed = 0;
+    if (nh >= k.min_tracklet_hits) {
+      // owned hits lie only in the tiles that overlap [rin, rout]
+      const uint32_t t0 = (uint32_t)d.tk_info[T + i] / tile_rows, t1 = (uint32_t)d.tk_info[2 * T + i] / tile_rows;
+      uint32_t owned = 0;
+      for (uint32_t tt = t0; tt <= t1; ++tt) {
+        const uint32_t c = d.own_part[(size_t)tt * T + i];
+        d.own_part[(size_t)tt * T + i] = (uint8_t)owned;   // prefix before this tile
+        owned += c;
+      }
+      const float need = k.min_owned_frac * (float)nh;
+      if ((int32_t)owned >= k.min_track_hits && (float)owned >= need)
+        packed = ((unsigned long long)owned << 32) | 1ull;
+    }
+    d.tk_pack[i] = packed;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_emit_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
+  extern __shared__ uint32_t wt[];
+  const Tile tl = tile_of(d, tile_rows, n_tiles);
+  const uint32_t T = d.tcap, tt = blockIdx.x % n_tiles;
+  for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) wt[j] = d.W[tl.first + j];
+  __syncthreads();
+  for (uint32_t i = tl.ts + threadIdx.x; i < tl.te; i += blockDim.x) {
+    const unsigned long long pk = d.tk_pack[i];
+    if (!(pk & 1ull)) continue;
+    const unsigned long long pre = d.tk_scan[i];
+    const uint32_t ti = (uint32_t)(pre & 0xFFFFFFFFull);
+    const unsigned long long co = pre >> 32;
+    if (ti >= d.max_tracks || co + (pk >> 32) > d.max_track_clusters) continue;   // flagged in k_finish
+    const int32_t nh = d.tk_info[i];
+    const int32_t a = max((int32_t)tl.ra, d.tk_info[T + i]), b = min((int32_t)tl.rb - 1, d.tk_info[2 * T + i]);
+    if (a > b) continue;
+    const uint32_t key = key32((uint32_t)nh, i);
+    uint32_t o = (uint32_t)co + d.own_part[(size_t)tt * T + i];
+    for (int32_t r = a; r <= b; ++r) {
+      const int32_t h = d.tk_rowhit[(size_t)r * T + i];
+      if (h >= 0 && wt[(uint32_t)h - tl.first] == key) d.out_clusters[o++] = d.sid[h];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_records(DevPtrs d, KfConst k) {
+  const uint32_t nt = n_tracklets(d), T = d.tcap;
+  const XcdSched sch = xcd_sched(nt);
+  for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
+    const uint32_t i = vb * blockDim.x + threadIdx.x;
+    if (i >= nt) continue;
+    const unsigned long long pk = d.tk_pack[i];
+    if (!(pk & 1ull)) continue;
+    const unsigned long long pre = d.tk_scan[i];
+    const uint32_t ti = (uint32_t)(pre & 0xFFFFFFFFull);
+    const unsigned long long co = pre >> 32;
+    if (ti >= d.max_tracks || co + (pk >> 32) > d.max_track_clusters) continue;
+    const int32_t nh = d.tk_info[i];
+    d.out_sector[ti] = d.start_sr[i] / d.R;
+    d.out_start[ti] = d.start_pos[i];
+    d.out_first[ti] = (uint32_t)co;
+    d.out_xref[ti] = d.rows[d.tk_info[T + i]].x;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) d.out_param[(size_t)ti * 5 + q] = d.tk_param[(size_t)q * T + i];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) d.out_cov[(size_t)ti * 15 + q] = d.tk_cov[(size_t)q * T + i];
+    d.out_chi2[ti] = d.tk_chi2[i];
+    d.out_ndf[ti] = 2 * nh - 5;
+  }
+}
+
+// ---- global-memory variant for rows too large for an LDS tile ----
 template <class Fn>
 __device__ __forceinline__ void for_rows(const DevPtrs& d, uint32_t i, int32_t rin, int32_t rout, Fn fn) {
   const uint32_t T = d.tcap;
@@ -37,7 +184,11 @@ __device__ __forceinline__ void for_rows(const DevPtrs& d, uint32_t i, int32_t r
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_claim(DevPtrs d, KfConst k) {
+__global__ void __launch_bounds__(kThreads) k_clear_w(DevPtrs d) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < d.N; j += gridDim.x * blockDim.x) d.W[j] = 0u;
+}
+
+__global__ void __launch_bounds__(kThreads) k_claim_g(DevPtrs d, KfConst k) {
   const uint32_t nt = n_tracklets(d), T = d.tcap;
   const XcdSched sch = xcd_sched(nt);
   for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
@@ -45,24 +196,14 @@ __global__ void __launch_bounds__(kThreads) k_claim(DevPtrs d, KfConst k) {
     if (i >= nt) continue;
     const int32_t nh = d.tk_info[i];
     if (nh < k.min_tracklet_hits) continue;
-    const unsigned long long key = key_of((uint32_t)nh, d.start_pos[i]);
-    const int32_t rin = d.tk_info[T + i], rout = d.tk_info[2 * T + i];
-    for (int32_t r = rin; r <= rout; r += kUnroll) {
-      int32_t h[kUnroll];
-      unsigned long long w[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) h[u] = (r + u <= rout) ? d.tk_rowhit[(size_t)(r + u) * T + i] : -1;
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) w[u] = h[u] >= 0 ? d.W[h[u]] : ~0ull;
-      // max is monotone: skip the atomic where the word already holds a larger key
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (w[u] < key) atomicMax(&d.W[h[u]], key);
-    }
+    const uint32_t key = key32((uint32_t)nh, i);
+    for_rows(d, i, d.tk_info[T + i], d.tk_info[2 * T + i], [&](int32_t h) {
+      if (h >= 0 && d.W[h] < key) atomicMax(&d.W[h], key);   // max is monotone: skip when already larger
+    });
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_own(DevPtrs d, KfConst k) {
+__global__ void __launch_bounds__(kThreads) k_own_g(DevPtrs d, KfConst k) {
   const uint32_t nt = n_tracklets(d), T = d.tcap;
   const XcdSched sch = xcd_sched(nt);
   for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
@@ -71,10 +212,10 @@ __global__ void __launch_bounds__(kThreads) k_own(DevPtrs d, KfConst k) {
     const int32_t nh = d.tk_info[i];
     unsigned long long packed = 0;
     if (nh >= k.min_tracklet_hits) {
-      const unsigned long long key = key_of((uint32_t)nh, d.start_pos[i]);
-      const int32_t rin = d.tk_info[T + i], rout = d.tk_info[2 * T + i];
+      const uint32_t key = key32((uint32_t)nh, i);
       uint32_t owned = 0;
-      for_rows(d, i, rin, rout, [&](int32_t h) { owned += (h >= 0 && d.W[h] == key) ? 1u : 0u; });
+      for_rows(d, i, d.tk_info[T + i], d.tk_info[2 * T + i],
+               [&](int32_t h) { owned += (h >= 0 && d.W[h] == key) ? 1u : 0u; });
       const float need = k.min_owned_frac * (float)nh;
       if ((int32_t)owned >= k.min_track_hits && (float)owned >= need)
         packed = ((unsigned long long)owned << 32) | 1ull;
@@ -83,7 +224,7 @@ __global__ void __launch_bounds__(kThreads) k_own(DevPtrs d, KfConst k) {
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_emit(DevPtrs d, KfConst k) {
+__global__ void __launch_bounds__(kThreads) k_emit_g(DevPtrs d, KfConst k) {
   const uint32_t nt = n_tracklets(d), T = d.tcap;
   const XcdSched sch = xcd_sched(nt);
   for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
@@ -94,25 +235,12 @@ __global__ void __launch_bounds__(kThreads) k_emit(DevPtrs d, KfConst k) {
     const unsigned long long pre = d.tk_scan[i];
     const uint32_t ti = (uint32_t)(pre & 0xFFFFFFFFull);
     const unsigned long long co = pre >> 32;
-    const uint32_t owned = (uint32_t)(pk >> 32);
-    if (ti >= d.max_tracks || co + owned > d.max_track_clusters) continue;   // flagged in k_finish
-    const int32_t nh = d.tk_info[i];
-    const unsigned long long key = key_of((uint32_t)nh, d.start_pos[i]);
-    const int32_t rin = d.tk_info[T + i], rout = d.tk_info[2 * T + i];
+    if (ti >= d.max_tracks || co + (pk >> 32) > d.max_track_clusters) continue;
+    const uint32_t key = key32((uint32_t)d.tk_info[i], i);
     uint32_t o = (uint32_t)co;
-    for_rows(d, i, rin, rout, [&](int32_t h) {
+    for_rows(d, i, d.tk_info[T + i], d.tk_info[2 * T + i], [&](int32_t h) {
       if (h >= 0 && d.W[h] == key) d.out_clusters[o++] = d.sid[h];
     });
-    d.out_sector[ti] = d.start_sr[i] / d.R;
-    d.out_start[ti] = d.start_pos[i];
-    d.out_first[ti] = (uint32_t)co;
-    d.out_xref[ti] = d.rows[rin].x;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) d.out_param[(size_t)ti * 5 + q] = d.tk_param[(size_t)q * T + i];
-#pragma unroll
-    for (int q = 0; q < 15; ++q) d.out_cov[(size_t)ti * 15 + q] = d.tk_cov[(size_t)q * T + i];
-    d.out_chi2[ti] = d.tk_chi2[i];
-    d.out_ndf[ti] = 2 * nh - 5;
   }
 }
 
@@ -132,14 +260,26 @@ __global__ void k_finish(DevPtrs d) {
 
 }  // namespace
 
-void launch_select(const DevPtrs& d, const KfConst& k, hipStream_t s) {
-  uint32_t blocks = (d.tcap + kThreads - 1) / kThreads;
-  if (blocks > 8192) blocks = 8192;
-  blocks = xcd_grid(blocks == 0 ? 1 : blocks);
-  hipLaunchKernelGGL(k_claim, dim3(blocks), dim3(kThreads), 0, s, d, k);
-  hipLaunchKernelGGL(k_own, dim3(blocks), dim3(kThreads), 0, s, d, k);
-  launch_scan_u64(d.tk_pack, d.tk_scan, &d.hdr->n_starts, d.tcap, d.scan_blocks, s);
-  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, d, k);
+void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipStream_t s) {
+  const uint32_t blocks = xcd_grid(std::min<uint32_t>(8192, std::max<uint32_t>(1, (d.tcap + kThreads - 1) / kThreads)));
+  if (tile_rows > 0 && d.S > 0) {
+    const uint32_t n_tiles = (d.R + tile_rows - 1) / tile_rows;
+    const size_t lds = (size_t)d.tile_cap * sizeof(uint32_t);
+    const dim3 tiles(d.S * n_tiles);
+    hipLaunchKernelGGL(k_claim_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
+    hipLaunchKernelGGL(k_own_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
+    hipLaunchKernelGGL(k_accept, dim3(blocks), dim3(kThreads), 0, s, d, k, tile_rows);
+    launch_scan_u64(d.tk_pack, d.tk_scan, &d.hdr->n_starts, d.tcap, d.scan_blocks, s);
+    hipLaunchKernelGGL(k_emit_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
+  } else {
+    hipLaunchKernelGGL(k_clear_w, dim3(xcd_grid(std::min<uint32_t>(8192, std::max<uint32_t>(1, (d.N + kThreads - 1) / kThreads)))),
+                       dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_claim_g, dim3(blocks), dim3(kThreads), 0, s, d, k);
+    hipLaunchKernelGGL(k_own_g, dim3(blocks), dim3(kThreads), 0, s, d, k);
+    launch_scan_u64(d.tk_pack, d.tk_scan, &d.hdr->n_starts, d.tcap, d.scan_blocks, s);
+    hipLaunchKernelGGL(k_emit_g, dim3(blocks), dim3(kThreads), 0, s, d, k);
+  }
+  hipLaunchKernelGGL(k_records, dim3(blocks), dim3(kThreads), 0, s, d, k);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, d);
 }
 

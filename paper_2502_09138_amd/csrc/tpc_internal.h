@@ -73,6 +73,7 @@ struct DevPtrs {
   uint32_t* row_start_off;   // [SR+1] exclusive scan
   uint32_t* start_pos;       // [Tcap]
   uint32_t* start_sr;        // [Tcap]
+  uint32_t* wave_off;        // [S+1] row-synchronous K5: first wave of each sector
   // C5
   int32_t* tk_rowhit;        // [R * Tcap]
   int32_t* tk_info;          // [4 * Tcap]: nHits, r_in, r_out, r0
@@ -80,7 +81,8 @@ struct DevPtrs {
   float* tk_cov;             // [15 * Tcap]
   float* tk_chi2;            // [Tcap]
   // C6
-  unsigned long long* W;     // [N]
+  uint32_t* W;               // [N] ownership word (32-bit key) per sorted position
+  uint8_t* own_part;         // [R * Tcap] owned hits of a tracklet per selector tile (then prefixes)
   unsigned long long* tk_pack;   // [Tcap] (owned << 32) | accepted
   unsigned long long* tk_scan;   // [Tcap + 1] exclusive scan of tk_pack
   // outputs
@@ -99,8 +101,10 @@ struct DevPtrs {
   // sizes
   int32_t grid_k;
   float rho;                 // (sigma_y / sigma_z)^2, float32
+  int32_t k5_mode;           // 0 auto, 1 per-lane gathers, 2 row-synchronous
   uint32_t S, R, SR, N;
   uint32_t tcap;
+  uint32_t tile_cap;         // LDS words of one selector tile (max hits in a sector's row block)
   uint32_t max_tracks;
   uint64_t max_track_clusters;
 };
@@ -112,8 +116,8 @@ constexpr int kScanMaxBlocks = 8192;               // supports scans of up to 8M
 void launch_grid(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
 void launch_links(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
 void launch_clean_starts(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
-void launch_tracklets(const DevPtrs& d, const KfConst& k, hipStream_t s);
-void launch_select(const DevPtrs& d, const KfConst& k, hipStream_t s);
+void launch_tracklets(const DevPtrs& d, const KfConst& k, uint32_t max_row_hits, hipStream_t s);
+void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipStream_t s);
 // exclusive scans; n read from *n_dev when n_dev != nullptr (then n_max bounds the grid)
 void launch_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, unsigned long long* blocks, hipStream_t s);
 void launch_scan_u64(const unsigned long long* in, unsigned long long* out, const uint32_t* n_dev, uint32_t n_max,

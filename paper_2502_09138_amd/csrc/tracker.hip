@@ -38,10 +38,12 @@ tpc_status fail(tpc_status st, const std::string& msg) {
 
 constexpr double kCB = 0.00299792458;
 constexpr uint64_t kAlign = 256;
+constexpr uint32_t kSelectTileWords = 12288;   // 48 KB of LDS per selector tile
 
 struct Layout {   // byte offsets of every workspace buffer
   uint64_t row_off, rows, secs, row_dims, row_meta, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
-      row_start_off, start_pos, start_sr, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, W, tk_pack, tk_scan,
+      row_start_off, start_pos, start_sr, wave_off, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, W, own_part, tk_pack,
+      tk_scan,
       out_sector, out_start, out_first, out_clusters, out_xref, out_param, out_cov, out_chi2, out_ndf, scan_blocks,
       hdr, in_y, in_z, total;
 };
@@ -88,12 +90,14 @@ Layout layout_of(const Caps& k) {
   L.row_start_off = take((k.SRmax + 1) * 4);
   L.start_pos = take(k.T * 4);
   L.start_sr = take(k.T * 4);
+  L.wave_off = take(((uint64_t)k.Smax + 1) * 4);
   L.tk_rowhit = take((uint64_t)k.R * k.T * 4);
   L.tk_info = take(4 * k.T * 4);
   L.tk_param = take(5 * k.T * 4);
   L.tk_cov = take(15 * k.T * 4);
   L.tk_chi2 = take(k.T * 4);
-  L.W = take(k.N * 8);
+  L.W = take(k.N * 4);
+  L.own_part = take((uint64_t)k.R * k.T);
   L.tk_pack = take(k.T * 8);
   L.tk_scan = take((k.T + 1) * 8);
   L.out_sector = take(k.MT * 4);
@@ -131,6 +135,7 @@ std::string validate_config(const tpc_tracker_config* c) {
   if (!(c->c0_sinphi > 0.0 && c->c0_tanl > 0.0 && c->c0_qpt > 0.0)) return "initial variances must be > 0";
   if (c->max_miss < 0 || c->min_tracklet_hits < 3 || c->min_track_hits < 1) return "hit-count cuts out of range";
   if (c->max_sectors < 1) return "max_sectors must be >= 1";
+  if (c->tracklet_schedule < 0 || c->tracklet_schedule > 2) return "tracklet_schedule must be 0, 1 or 2";
   if (c->max_clusters >= (1ull << 31)) return "max_clusters must be < 2^31";
   const Caps k = caps_of(*c);
   if (k.T > (uint64_t)kScanBlock * kScanMaxBlocks) return "max_tracklets exceeds 8M";
@@ -314,12 +319,14 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   d.row_start_off = (uint32_t*)(w + lay.row_start_off);
   d.start_pos = (uint32_t*)(w + lay.start_pos);
   d.start_sr = (uint32_t*)(w + lay.start_sr);
+  d.wave_off = (uint32_t*)(w + lay.wave_off);
   d.tk_rowhit = (int32_t*)(w + lay.tk_rowhit);
   d.tk_info = (int32_t*)(w + lay.tk_info);
   d.tk_param = (float*)(w + lay.tk_param);
   d.tk_cov = (float*)(w + lay.tk_cov);
   d.tk_chi2 = (float*)(w + lay.tk_chi2);
-  d.W = (unsigned long long*)(w + lay.W);
+  d.W = (uint32_t*)(w + lay.W);
+  d.own_part = (uint8_t*)(w + lay.own_part);
   d.tk_pack = (unsigned long long*)(w + lay.tk_pack);
   d.tk_scan = (unsigned long long*)(w + lay.tk_scan);
   d.out_sector = (uint32_t*)(w + lay.out_sector);
@@ -334,6 +341,7 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   d.scan_blocks = (unsigned long long*)(w + lay.scan_blocks);
   d.hdr = (ResultHeader*)(w + lay.hdr);
   d.grid_k = cfg->grid_hits_per_bin;
+  d.k5_mode = cfg->tracklet_schedule;
   d.rho = k.rho;
   d.R = R;
   d.tcap = (uint32_t)caps.T;
@@ -456,6 +464,23 @@ tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t*
     d.y = f->y;
     d.z = f->z;
   }
+  // selector tile: the most rows per tile (8, 4, 2, 1) whose largest sector row
+  // block fits the LDS budget; 0 = rows too large, global-memory selector.
+  // Per-tile owned counts are bytes, so tiles need at most 255 rows per sector.
+  uint32_t tile_rows = 0, tile_cap = 0;
+  for (uint32_t tr = 8; tr >= 1 && tile_rows == 0 && R <= 255; tr /= 2) {
+    uint32_t mx = 0;
+    for (uint32_t s = 0; s < S; ++s)
+      for (uint32_t ra = 0; ra < R; ra += tr) {
+        const uint32_t rb = std::min(R, ra + tr);
+        mx = std::max(mx, f->row_offsets[s * R + rb] - f->row_offsets[s * R + ra]);
+      }
+    if (mx <= kSelectTileWords) {
+      tile_rows = tr;
+      tile_cap = std::max(mx, 1u);
+    }
+  }
+  d.tile_cap = tile_cap;
   const bool tm = t->timing;
   if (tm) HIP_TRY(hipEventRecord(t->ev[0], st));
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, st, d.hdr);
@@ -465,9 +490,9 @@ tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t*
   if (tm) HIP_TRY(hipEventRecord(t->ev[2], st));
   launch_clean_starts(d, max_row, st);
   if (tm) HIP_TRY(hipEventRecord(t->ev[3], st));
-  launch_tracklets(d, t->kc, st);
+  launch_tracklets(d, t->kc, max_row, st);
   if (tm) HIP_TRY(hipEventRecord(t->ev[4], st));
-  launch_select(d, t->kc, st);
+  launch_select(d, t->kc, tile_rows, st);
   if (tm) HIP_TRY(hipEventRecord(t->ev[5], st));
   HIP_TRY(hipMemcpyAsync(t->h_hdr, d.hdr, sizeof(ResultHeader), hipMemcpyDeviceToHost, st));
   if (tm) HIP_TRY(hipEventRecord(t->ev[6], st));

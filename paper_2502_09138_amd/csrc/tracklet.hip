@@ -203,6 +203,39 @@ __device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const R
   return best;
 }
 
+// The same search over a row staged in LDS: (y, z) of the row's hits at
+// yz[q - first] and its bin starts (global positions) in bs[].
+__device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* bs, uint32_t first, uint2 meta,
+                                              const RowK& rk, const SectorConst& sc, const Trk& t, const KfConst& k,
+                                              float zref) {
+  const float sy2 = t.c[0] + k.vy, sz2 = t.c[2] + k.vz;
+  const float wy = fminf(k.gate * fsqrt(sy2), k.cap), wz = fminf(k.gate * fsqrt(sz2), k.cap);
+  const float isy = frcp(sy2), isz = frcp(sz2);
+  const float yp = t.p[0], zp = t.p[1];
+  const float za = zref + zp;
+  const int ny = (int)(meta.y & 0xFFFFu), nz = (int)(meta.y >> 16);
+  const int iy0 = bin1((yp - wy) - kWinPad, rk.y_lo, rk.inv_wy, ny);
+  const int iy1 = bin1((yp + wy) + kWinPad, rk.y_lo, rk.inv_wy, ny);
+  const int iz0 = bin1((za - wz) - kWinPad, sc.z_lo, sc.inv_wz, nz);
+  const int iz1 = bin1((za + wz) + kWinPad, sc.z_lo, sc.inv_wz, nz);
+  int32_t best = -1;
+  float bd = 0.0f;
+  for (int iz = iz0; iz <= iz1; ++iz) {
+    const uint32_t lo = bs[iz * ny + iy0], hi = bs[iz * ny + iy1 + 1];
+    for (uint32_t q = lo; q < hi; ++q) {
+      const float2 h = yz[q - first];
+      const float dy = h.x - yp, dz = (h.y - zref) - zp;
+      if (!(fabsf(dy) <= wy && fabsf(dz) <= wz)) continue;
+      const float dd = dy * dy * isy + dz * dz * isz;
+      if (best < 0 || dd < bd) {
+        best = (int32_t)q;
+        bd = dd;
+      }
+    }
+  }
+  return best;
+}
+
 // Three-point seed; false on failure.
 __device__ __forceinline__ bool seed3(float x0, float2 h0, float xm, float2 hm, float xl, float2 hl, const KfConst& k,
                                       Trk& t) {
@@ -419,14 +452,307 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
   if (my_steps) atomicAdd(&d.hdr->n_steps, my_steps);
 }
 
+// ---------------------------------------------------------------------------
+// Row-synchronous schedule ("coalesced row-grid reads").  A wave takes up to
+// 64 tracklets of ONE sector.  After each lane has walked its chain and built
+// its seed, the wave sweeps the rows in lockstep -- outward, then inward --
+// and at every row stages that row's (y, z) and bin starts in LDS with one
+// coalesced load shared by all lanes; the loads for the next row are issued
+// before the current row's Kalman step and land in registers while it runs.
+// Every search and every measurement read then hits LDS, which takes the
+// dependent global-memory round trips out of the per-row critical path.  Rows
+// larger than the stage fall back to global-memory search for that row.
+constexpr int kStageHits = 320;
+constexpr int kStageBins = kStageHits + 2;                       // nBins + 1 <= N_r + 1
+constexpr int kPreYz = (kStageHits + kThreads - 1) / kThreads;   // per-lane prefetch slots
+constexpr int kPreBs = (kStageBins + kThreads - 1) / kThreads;
+
+struct Stage {
+  uint32_t first, n;
+  uint2 meta;
+  bool fits;
+};
+
+struct Prefetch {
+  float2 yz[kPreYz];
+  uint32_t bs[kPreBs];
+  Stage st;
+};
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, kWave));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, kWave));
+  return v;
+}
+
+// Issue the loads of row sr into registers (no LDS traffic yet).
+__device__ __forceinline__ void prefetch_row(const DevPtrs& d, uint32_t sr, Prefetch& pf) {
+  const uint32_t lane = threadIdx.x;
+  pf.st.first = d.row_off[sr];
+  pf.st.n = d.row_off[sr + 1] - pf.st.first;
+  pf.st.meta = d.row_meta[sr];
+  pf.st.fits = pf.st.n <= (uint32_t)kStageHits;
+  if (!pf.st.fits) return;
+  const uint32_t nb1 = (pf.st.meta.y & 0xFFFFu) * (pf.st.meta.y >> 16) + 1;
+#pragma unroll
+  for (int m = 0; m < kPreYz; ++m) {
+    const uint32_t j = lane + m * kThreads;
+    if (j < pf.st.n) pf.yz[m] = d.syz[pf.st.first + j];
+  }
+#pragma unroll
+  for (int m = 0; m < kPreBs; ++m) {
+    const uint32_t j = lane + m * kThreads;
+    if (j < nb1) pf.bs[m] = d.bin_start[pf.st.meta.x + j];
+  }
+}
+
+// Write prefetched registers to the LDS stage (call between two barriers).
+__device__ __forceinline__ void commit_row(const Prefetch& pf, float2* yz_s, uint32_t* bs_s, Stage& st) {
+  const uint32_t lane = threadIdx.x;
+  st = pf.st;
+  if (!st.fits) return;
+  const uint32_t nb1 = (st.meta.y & 0xFFFFu) * (st.meta.y >> 16) + 1;
+#pragma unroll
+  for (int m = 0; m < kPreYz; ++m) {
+    const uint32_t j = lane + m * kThreads;
+    if (j < st.n) yz_s[j] = pf.yz[m];
+  }
+#pragma unroll
+  for (int m = 0; m < kPreBs; ++m) {
+    const uint32_t j = lane + m * kThreads;
+    if (j < nb1) bs_s[j] = pf.bs[m];
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k) {
+  __shared__ RowK lrows[kMaxRows];
+  __shared__ float2 yz_s[kStageHits];
+  __shared__ uint32_t bs_s[kStageBins];
+  load_rows(d, lrows);
+  const uint32_t R = d.R, T = d.tcap, S = d.S;
+  const uint32_t lane = threadIdx.x;
+  const uint32_t W = d.wave_off[S];
+  // XCD-contiguous ranges of waves (one wave per block, waves ordered by sector)
+  const uint32_t per = (W + kXcds - 1) / kXcds;
+  const uint32_t xcd = blockIdx.x % kXcds;
+  const uint32_t vend = min(W, (xcd + 1) * per);
+  unsigned long long my_steps = 0;
+  for (uint32_t v = xcd * per + blockIdx.x / kXcds; v < vend; v += gridDim.x / kXcds) {
+    // sector of wave v: last s with wave_off[s] <= v
+    uint32_t lo = 0, hi = S;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (d.wave_off[mid] <= v) lo = mid; else hi = mid;
+    }
+    const uint32_t sec = lo, srb = sec * R;
+    const uint32_t ts = min(d.row_start_off[srb], T), te = min(d.row_start_off[srb + R], T);
+    const uint32_t i = ts + (v - d.wave_off[sec]) * kThreads + lane;
+    const SectorConst sc = d.secs[sec];
+    int32_t* H = d.tk_rowhit + i;
+    // ---- per lane: chain walk and seed ----
+    bool ok = i < te;
+    uint32_t r0 = 0, rl = 0, n = 0;
+    float zref = 0.0f, chi2 = 0.0f, xprev = 0.0f;
+    Trk t;
+    if (ok) {
+      const uint32_t sr0 = d.start_sr[i];
+      r0 = sr0 % R;
+      int32_t p = (int32_t)d.start_pos[i];
+      int32_t plast = p;
+      while (p >= 0 && r0 + n < R) {
+        H[(size_t)(r0 + n) * T] = p;
+        plast = p;
+        ++n;
+        p = d.up1[p];
+      }
+      const uint32_t m = (n - 1) / 2;
+      rl = r0 + n - 1;
+      const int32_t pm = H[(size_t)(r0 + m) * T];
+      const float2 h0 = d.syz[d.start_pos[i]];
+      zref = h0.y;
+      if (seed3(lrows[r0].x, h0, lrows[r0 + m].x, d.syz[pm], lrows[rl].x, d.syz[plast], k, t)) {
+        set_c0(t, k);
+        xprev = lrows[r0].x;
+      } else {
+        d.tk_info[i] = -1;
+        ok = false;
+      }
+    }
+    uint32_t steps = ok ? n - 1 : 0;
+    // ---- outward sweep ----
+    bool up = ok, failed = false;
+    float pout[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
+    uint32_t rout = rl;
+    int miss = 0;
+    Stage st;
+    Prefetch pf;
+    uint32_t r = wave_min(up ? r0 + 1 : R);
+    if (r < R) {
+      prefetch_row(d, srb + r, pf);
+      commit_row(pf, yz_s, bs_s, st);
+      __syncthreads();
+    }
+    int32_t hnext = (up && r <= rl && r > r0) ? H[(size_t)r * T] : -1;
+    while (r < R && __any(up)) {
+      if (r + 1 < R) prefetch_row(d, srb + r + 1, pf);
+      const int32_t hchain = hnext;
+      hnext = (up && r + 1 <= rl && r + 1 > r0) ? H[(size_t)(r + 1) * T] : -1;
+      if (up && r > r0) {
+        const RowK rk = lrows[r];
+        const bool chain = r <= rl;
+        if (!chain) ++steps;
+        if (!propagate(t, rk.x - xprev, k)) {
+          up = false;
+          failed = chain;
+        } else {
+          xprev = rk.x;
+          if (!chain && fabsf(t.p[0]) > rk.half_y + k.margin) {
+            up = false;
+          } else {
+            int32_t h = hchain;
+            if (!chain) {
+              h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref)
+                          : search(d, srb + r, rk, sc, t, k, zref);
+              H[(size_t)r * T] = h;
+            }
+            if (h >= 0) {
+              const float2 hm = st.fits ? yz_s[(uint32_t)h - st.first] : d.syz[h];
+              update(t, hm.x, hm.y - zref, k, chi2);
+              if (r >= rl) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
+                rout = r;
+                miss = 0;
+              }
+            } else if (++miss > k.max_miss) {
+              up = false;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (r + 1 < R) commit_row(pf, yz_s, bs_s, st);
+      __syncthreads();
+      ++r;
+    }
+    if (failed) {
+      d.tk_info[i] = -2;
+      ok = false;
+    }
+    // ---- inward sweep from each lane's outermost hit, fresh covariance ----
+    bool down = ok;
+    int nh = 1;
+    Trk snap;
+    uint32_t rin = rout;
+    if (down) {
+      const float2 ho = d.syz[H[(size_t)rout * T]];
+#pragma unroll
+      for (int q = 2; q < 5; ++q) t.p[q] = pout[q];
+      t.p[0] = ho.x;
+      t.p[1] = ho.y - zref;
+      set_c0(t, k);
+      chi2 = 0.0f;
+      snap = t;
+      xprev = lrows[rout].x;
+      miss = 0;
+    }
+    int32_t rr = (int32_t)wave_max(down ? rout : 0) - 1;
+    if (rr >= 0) {
+      prefetch_row(d, srb + (uint32_t)rr, pf);
+      commit_row(pf, yz_s, bs_s, st);
+      __syncthreads();
+    }
+    hnext = (down && rr >= (int32_t)r0 && rr < (int32_t)rout) ? H[(size_t)rr * T] : -1;
+    while (rr >= 0 && __any(down)) {
+      if (rr > 0) prefetch_row(d, srb + (uint32_t)rr - 1, pf);
+      const int32_t hrow = hnext;
+      hnext = (down && rr - 1 >= (int32_t)r0 && rr - 1 < (int32_t)rout) ? H[(size_t)(rr - 1) * T] : -1;
+      if (down && rr < (int32_t)rout) {
+        const RowK rk = lrows[rr];
+        ++steps;
+        if (!propagate(t, rk.x - xprev, k)) {
+          down = false;
+        } else {
+          xprev = rk.x;
+          const bool below = (uint32_t)rr < r0;
+          if (below && fabsf(t.p[0]) > rk.half_y + k.margin) {
+            down = false;
+          } else {
+            int32_t h = below ? -1 : hrow;
+            if (h < 0)
+              h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref)
+                          : search(d, srb + (uint32_t)rr, rk, sc, t, k, zref);
+            H[(size_t)rr * T] = h;
+            if (h >= 0) {
+              const float2 hm = st.fits ? yz_s[(uint32_t)h - st.first] : d.syz[h];
+              update(t, hm.x, hm.y - zref, k, chi2);
+              ++nh;
+              snap = t;
+              rin = (uint32_t)rr;
+              if (below) miss = 0;
+            } else if (below && ++miss > k.max_miss) {
+              down = false;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (rr > 0) commit_row(pf, yz_s, bs_s, st);
+      __syncthreads();
+      --rr;
+    }
+    if (ok) {
+      store_tracklet(d, i, nh, rin, rout, r0, snap, chi2, zref);
+      my_steps += steps;
+    }
+  }
+  if (my_steps) atomicAdd(&d.hdr->n_steps, my_steps);
+}
+
+// Waves of the row-synchronous schedule: ceil(tracklets of sector s / 64) per
+// sector, prefix-summed (one block).
+__global__ void __launch_bounds__(1024) k_waves(DevPtrs d) {
+  __shared__ uint32_t wsum[1024 / kWave];
+  const uint32_t S = d.S, R = d.R, T = d.tcap;
+  const uint32_t per = (S + blockDim.x - 1) / blockDim.x;
+  const uint32_t s0 = min(S, threadIdx.x * per), s1 = min(S, s0 + per);
+  uint32_t sum = 0;
+  for (uint32_t s = s0; s < s1; ++s) {
+    const uint32_t a = min(d.row_start_off[s * R], T), b = min(d.row_start_off[(s + 1) * R], T);
+    sum += (b - a + kThreads - 1) / kThreads;
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan<uint32_t>(sum, wsum, &total);
+  for (uint32_t s = s0; s < s1; ++s) {
+    d.wave_off[s] = run;
+    const uint32_t a = min(d.row_start_off[s * R], T), b = min(d.row_start_off[(s + 1) * R], T);
+    run += (b - a + kThreads - 1) / kThreads;
+  }
+  if (threadIdx.x == 0) d.wave_off[S] = total;
+}
+
 }  // namespace
 
-void launch_tracklets(const DevPtrs& d, const KfConst& k, hipStream_t s) {
+void launch_tracklets(const DevPtrs& d, const KfConst& k, uint32_t max_row_hits, hipStream_t s) {
   if (d.tcap == 0) return;
+  const bool rowsync = d.k5_mode == 2 || (d.k5_mode == 0 && max_row_hits <= (uint32_t)kStageHits);
+  if (rowsync) {
+    hipLaunchKernelGGL(k_waves, dim3(1), dim3(1024), 0, s, d);
+    uint32_t blocks = (d.tcap + kThreads - 1) / kThreads + d.S;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_tracklets_rs, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
+    return;
+  }
   uint32_t blocks = (d.tcap + kThreads - 1) / kThreads;
   if (blocks > 16384) blocks = 16384;
-  blocks = xcd_grid(blocks);
-  hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(kThreads), 0, s, d, k);
+  hipLaunchKernelGGL(k_tracklets, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
 }
 
 }  // namespace tpc

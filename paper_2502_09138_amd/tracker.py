@@ -48,6 +48,7 @@ class _Config(C.Structure):
         ("gate_nsigma", C.c_double), ("win_cap", C.c_double), ("edge_margin", C.c_double),
         ("max_miss", C.c_int32), ("min_tracklet_hits", C.c_int32), ("min_track_hits", C.c_int32),
         ("min_owned_frac", C.c_double),
+        ("tracklet_schedule", C.c_int32),
         ("max_sectors", C.c_uint32), ("max_clusters", C.c_uint64), ("max_tracklets", C.c_uint64),
         ("max_tracks", C.c_uint64), ("max_track_clusters", C.c_uint64),
         ("device", C.c_int32), ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64),
@@ -121,7 +122,7 @@ def _check(st):
 
 
 def make_config(cfg: TrackerConfig, *, max_clusters, max_sectors=36, max_tracklets=0, max_tracks=0,
-                max_track_clusters=0, device=0):
+                max_track_clusters=0, device=0, tracklet_schedule=0):
     """Fill the C config struct; returns (struct, keep-alive arrays)."""
     c = _Config()
     load().tpc_default_config(C.byref(c))
@@ -141,6 +142,7 @@ def make_config(cfg: TrackerConfig, *, max_clusters, max_sectors=36, max_trackle
     c.max_tracks = max_tracks
     c.max_track_clusters = max_track_clusters
     c.device = device
+    c.tracklet_schedule = tracklet_schedule
     return c, (row_x, row_half_y)
 
 
@@ -167,7 +169,7 @@ class Tracker:
     """One tracker on one GPU; workspace and stream come from torch."""
 
     def __init__(self, cfg: TrackerConfig | None = None, *, max_clusters, max_sectors=36, max_tracklets=0,
-                 max_tracks=0, max_track_clusters=0, device=0, stream=None):
+                 max_tracks=0, max_track_clusters=0, device=0, stream=None, tracklet_schedule=0):
         import torch
         self._torch = torch
         L = load()
@@ -177,7 +179,8 @@ class Tracker:
         self.device = torch.device("cuda", device)
         c, self._keep = make_config(cfg, max_clusters=max_clusters, max_sectors=max_sectors,
                                     max_tracklets=max_tracklets, max_tracks=max_tracks,
-                                    max_track_clusters=max_track_clusters, device=device)
+                                    max_track_clusters=max_track_clusters, device=device,
+                                    tracklet_schedule=tracklet_schedule)
         nbytes = L.tpc_workspace_bytes(C.byref(c))
         if nbytes == 0:
             raise TrackerError(TPC_E_INVAL, "invalid tracker configuration")
