@@ -15,7 +15,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr uint32_t kLdsRowCap = 4096;        // rows up to this many hits run from LDS
-constexpr float kMaxCoord = 16384.0f;
 
 struct RowArrays {   // cnt[nb+1], key[n], slot[n], tmp[n]
   uint32_t* cnt;
@@ -70,6 +69,8 @@ __device__ void grid_row(const DevPtrs& d, uint32_t sr, const RowArrays& A, uint
   // row-local bin starts -> global sorted positions (in place when cnt is the bin_start row itself)
   const uint32_t base = bin_base(d, sr);
   for (uint32_t b = threadIdx.x; b <= nb; b += blockDim.x) d.bin_start[base + b] = a + A.cnt[b];
+  // the row's entries of the neighbour finder's tile -> row map
+  for (uint32_t t = d.tile_off[sr] + threadIdx.x; t < d.tile_off[sr + 1]; t += blockDim.x) d.tile_sr[t] = sr;
 }
 
 __global__ void __launch_bounds__(kThreads) k_grid_lds(DevPtrs d, uint32_t cap) {

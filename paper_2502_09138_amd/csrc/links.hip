@@ -1,10 +1,15 @@
 // K2: neighbour finder -- step C2 of the tracker definition.
 //
-// One workgroup per (sector, row).  The two adjacent rows (r-1, r+1) are
-// staged in LDS -- their (y, z) pairs and bin starts -- so every candidate
-// test of the row's hits reads LDS instead of scattered L2 lines.  Rows too
-// large for the LDS budget read the same arrays from global memory.  All
-// window tests and the pair deviation use float32 with contraction off, in
+// One wave per tile of up to 64 consecutive hits of one row (so every lane
+// owns one hit, whatever the row size).  Rows are sorted z-line-major, so the
+// candidates any hit of the tile can reach in an adjacent row lie in one
+// contiguous run of that row's z-lines: the z-lines covering the tile's
+// [z_min - w_z, z_max + w_z] (the same padded window and float32 bin rule the
+// per-hit search uses, so every per-hit range is inside the staged run).  The
+// run's hits and bin starts are staged into LDS with coalesced loads and all
+// candidate tests read LDS; a run larger than the stage reads global memory.
+//
+// All window tests and the pair deviation use float32 with contraction off, in
 // the order the definition writes them, so the argmin is bit-identical to any
 // other evaluation of the definition.
 #include "device_common.h"
@@ -12,13 +17,15 @@
 namespace tpc {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr uint32_t kLdsRowCap = 3072;    // hits per staged row
+constexpr int kThreads = 64;             // one wave; one hit per lane
+constexpr uint32_t kSliceHits = 256;     // staged hits per adjacent row
+constexpr uint32_t kSliceBins = 256;     // staged bin starts per adjacent row
 
 struct RowView {
   const float2* yz;        // indexed by position - off
-  const uint32_t* bs;      // bin starts (global positions), nb+1 entries
-  uint32_t off;            // global sorted position of the row's first hit
+  const uint32_t* bs;      // bin starts (global positions), indexed by bin - bofs
+  uint32_t off;            // global sorted position of yz[0]
+  int bofs;                // first bin held in bs
   int ny, nz;
   float y_lo, inv_wy, z_lo, inv_wz;
 };
@@ -31,129 +38,149 @@ __device__ __forceinline__ void for_window(const RowView& v, float y, float z, f
   const int iy0 = bin1(y - py, v.y_lo, v.inv_wy, v.ny), iy1 = bin1(y + py, v.y_lo, v.inv_wy, v.ny);
   const int iz0 = bin1(z - pz, v.z_lo, v.inv_wz, v.nz), iz1 = bin1(z + pz, v.z_lo, v.inv_wz, v.nz);
   for (int iz = iz0; iz <= iz1; ++iz) {
-    const uint32_t lo = v.bs[iz * v.ny + iy0] - v.off, hi = v.bs[iz * v.ny + iy1 + 1] - v.off;
+    const uint32_t lo = v.bs[iz * v.ny + iy0 - v.bofs] - v.off, hi = v.bs[iz * v.ny + iy1 + 1 - v.bofs] - v.off;
     for (uint32_t q = lo; q < hi; ++q) fn(q);
   }
 }
 
-__device__ __forceinline__ void row_view(const DevPtrs& d, uint32_t sr, RowView& v) {
+// Candidate slots per lane for the passing hits of row r+1 (mean 1.6, max 7
+// on a central event); a hit with more falls back to rescanning the window.
+constexpr int kUpSlots = 8;
+
+// Links of one hit (sorted position p, coordinates h) of row rc between rows dn and up.
+__device__ __forceinline__ void link_hit(const DevPtrs& d, uint32_t p, float2 h, const RowView& dn, const RowView& up,
+                                         const RowConst& rc, float rho, uint16_t* slots) {
+#pragma clang fp contract(off)
+  const float t = rc.t;
+  int32_t bu = -1, bd = -1;
+  float best = 0.0f;
+  // passing candidates of row r+1, collected once
+  int nu = 0;
+  for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu) {
+    const float2 pu = up.yz[qu];
+    if (!(fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up)) return;
+    if (nu < kUpSlots) slots[nu] = (uint16_t)qu;
+    ++nu;
+  });
+  if (nu == 0) {
+    d.up0[p] = -1;
+    d.down0[p] = -1;
+    return;
+  }
+  auto pair = [&](const float2 pd, int32_t gd, uint32_t qu) {
+    const float2 pu = up.yz[qu];
+    const float yp = pd.x + t * (pu.x - pd.x);
+    const float zp = pd.y + t * (pu.y - pd.y);
+    const float ey = h.x - yp, ez = h.y - zp;
+    const float dev = ey * ey + rho * (ez * ez);
+    if (!(dev <= rc.dmax)) return;
+    const int32_t gu = (int32_t)(up.off + qu);
+    if (bu < 0 || dev < best || (dev == best && (gu < bu || (gu == bu && gd < bd)))) {
+      best = dev;
+      bu = gu;
+      bd = gd;
+    }
+  };
+  for_window(dn, h.x, h.y, rc.wy_dn, rc.wz_dn, [&](uint32_t qd) {
+    const float2 pd = dn.yz[qd];
+    if (!(fabsf(pd.x - h.x) <= rc.wy_dn && fabsf(pd.y - h.y) <= rc.wz_dn)) return;
+    const int32_t gd = (int32_t)(dn.off + qd);
+    if (nu <= kUpSlots) {
+      for (int k = 0; k < nu; ++k) pair(pd, gd, slots[k]);
+    } else {
+      for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu) {
+        const float2 pu = up.yz[qu];
+        if (fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up) pair(pd, gd, qu);
+      });
+    }
+  });
+  d.up0[p] = bu;
+  d.down0[p] = bd;
+}
+
+__device__ __forceinline__ float wave_minf(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// View of adjacent row sr restricted to the z-lines reachable from z in
+// [zmin, zmax] with window half-width wz; staged into (lyz, lbs) when it fits.
+__device__ __forceinline__ RowView adjacent_view(const DevPtrs& d, uint32_t sr, float zmin, float zmax, float wz,
+                                                 bool stage, float2* lyz, uint32_t* lbs) {
+#pragma clang fp contract(off)
   const uint32_t R = d.R;
   const RowConst rc = d.rows[sr % R];
   const SectorConst sc = d.secs[sr / R];
-  const uint32_t dims = d.row_dims[sr];
-  v.ny = (int)(dims & 0xFFFFu);
-  v.nz = (int)(dims >> 16);
-  v.off = d.row_off[sr];
+  const uint2 meta = d.row_meta[sr];
+  RowView v;
+  v.ny = (int)(meta.y & 0xFFFFu);
+  v.nz = (int)(meta.y >> 16);
   v.y_lo = rc.y_lo;
   v.inv_wy = rc.inv_wy;
   v.z_lo = sc.z_lo;
   v.inv_wz = sc.inv_wz;
-  v.yz = d.syz + v.off;
-  v.bs = d.bin_start + bin_base(d, sr);
-}
-
-// Stage a row's (y, z) and bin starts into LDS.
-__device__ __forceinline__ void stage(RowView& v, uint32_t n, float2* lyz, uint32_t* lbs) {
-  const uint32_t nb = (uint32_t)(v.ny * v.nz) + 1;
-  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) lyz[j] = v.yz[j];
-  for (uint32_t j = threadIdx.x; j < nb; j += blockDim.x) lbs[j] = v.bs[j];
-  v.yz = lyz;
-  v.bs = lbs;
-}
-
-// Candidate slots per thread for the passing hits of row r+1 (mean 1.6, max 7
-// on a central event); a hit with more falls back to rescanning the window.
-constexpr int kUpSlots = 8;
-
-__device__ __forceinline__ void links_row(const DevPtrs& d, uint32_t sr, const RowView& dn, const RowView& up,
-                                          const RowConst& rc, float rho, uint16_t* slots) {
-#pragma clang fp contract(off)
-  const uint32_t a = d.row_off[sr], n = d.row_off[sr + 1] - a;
-  const float t = rc.t;
-  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
-    const float2 h = d.syz[a + j];
-    int32_t bu = -1, bd = -1;
-    float best = 0.0f;
-    // passing candidates of row r+1, collected once
-    int nu = 0;
-    for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu) {
-      const float2 pu = up.yz[qu];
-      if (!(fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up)) return;
-      if (nu < kUpSlots) slots[nu] = (uint16_t)qu;
-      ++nu;
-    });
-    if (nu == 0) {
-      d.up0[a + j] = -1;
-      d.down0[a + j] = -1;
-      continue;
-    }
-    auto pair = [&](const float2 pd, int32_t gd, uint32_t qu) {
-      const float2 pu = up.yz[qu];
-      const float yp = pd.x + t * (pu.x - pd.x);
-      const float zp = pd.y + t * (pu.y - pd.y);
-      const float ey = h.x - yp, ez = h.y - zp;
-      const float dev = ey * ey + rho * (ez * ez);
-      if (!(dev <= rc.dmax)) return;
-      const int32_t gu = (int32_t)(up.off + qu);
-      if (bu < 0 || dev < best || (dev == best && (gu < bu || (gu == bu && gd < bd)))) {
-        best = dev;
-        bu = gu;
-        bd = gd;
-      }
-    };
-    for_window(dn, h.x, h.y, rc.wy_dn, rc.wz_dn, [&](uint32_t qd) {
-      const float2 pd = dn.yz[qd];
-      if (!(fabsf(pd.x - h.x) <= rc.wy_dn && fabsf(pd.y - h.y) <= rc.wz_dn)) return;
-      const int32_t gd = (int32_t)(dn.off + qd);
-      if (nu <= kUpSlots) {
-        for (int k = 0; k < nu; ++k) pair(pd, gd, slots[k]);
-      } else {
-        for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu) {
-          const float2 pu = up.yz[qu];
-          if (fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up) pair(pd, gd, qu);
-        });
-      }
-    });
-    d.up0[a + j] = bu;
-    d.down0[a + j] = bd;
+  const uint32_t* bs = d.bin_start + meta.x;
+  const float pz = wz + kWinPad;
+  const int iz0 = bin1(zmin - pz, v.z_lo, v.inv_wz, v.nz), iz1 = bin1(zmax + pz, v.z_lo, v.inv_wz, v.nz);
+  const uint32_t b0 = (uint32_t)(iz0 * v.ny), b1 = (uint32_t)((iz1 + 1) * v.ny);   // bins [b0, b1), starts [b0, b1]
+  const uint32_t s0 = bs[b0], s1 = bs[b1];
+  if (stage && s1 - s0 <= kSliceHits && b1 - b0 + 1 <= kSliceBins) {
+    for (uint32_t j = threadIdx.x; j < s1 - s0; j += kThreads) lyz[j] = d.syz[s0 + j];
+    for (uint32_t j = threadIdx.x; j <= b1 - b0; j += kThreads) lbs[j] = bs[b0 + j];
+    v.yz = lyz;
+    v.bs = lbs;
+    v.off = s0;
+    v.bofs = (int)b0;
+  } else {
+    v.off = d.row_off[sr];
+    v.yz = d.syz + v.off;
+    v.bs = bs;
+    v.bofs = 0;
   }
+  return v;
 }
 
-__global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, uint32_t cap, float rho) {
-  extern __shared__ uint32_t lds[];
+__global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho) {
+  __shared__ float2 lyz[2][kSliceHits];
+  __shared__ uint32_t lbs[2][kSliceBins];
   __shared__ uint16_t slots[kThreads][kUpSlots];
-  const uint32_t sr = blockIdx.x;
-  const uint32_t R = d.R;
-  const uint32_t row = sr % R;
-  const uint32_t a = d.row_off[sr], n = d.row_off[sr + 1] - a;
+  const uint32_t tile = blockIdx.x;
+  const uint32_t sr = d.tile_sr[tile], R = d.R, row = sr % R;
+  const uint32_t a = d.row_off[sr] + (tile - d.tile_off[sr]) * kThreads;
+  const uint32_t cnt = min((uint32_t)kThreads, d.row_off[sr + 1] - a);
+  const uint32_t lane = threadIdx.x;
+  const bool mine = lane < cnt;
+  const uint32_t p = a + lane;
   if (row == 0 || row + 1 >= R) {
-    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
-      d.up0[a + j] = -1;
-      d.down0[a + j] = -1;
+    if (mine) {
+      d.up0[p] = -1;
+      d.down0[p] = -1;
     }
     return;
   }
-  if (n == 0) return;
-  RowView dn, up;
-  row_view(d, sr - 1, dn);
-  row_view(d, sr + 1, up);
-  const uint32_t nd = d.row_off[sr] - dn.off, nu = d.row_off[sr + 2] - up.off;
-  // LDS layout: yz_dn[cap], yz_up[cap], bs_dn[cap+2], bs_up[cap+2]
-  float2* lyz = reinterpret_cast<float2*>(lds);
-  uint32_t* lbs = lds + 4 * cap;
-  if (nd <= cap) stage(dn, nd, lyz, lbs);
-  if (nu <= cap) stage(up, nu, lyz + cap, lbs + cap + 2);
+  const float2 h = mine ? d.syz[p] : make_float2(0.0f, 0.0f);
+  const float zmin = wave_minf(mine ? h.y : INFINITY), zmax = wave_maxf(mine ? h.y : -INFINITY);
+  // a non-finite or out-of-range z (flagged by K1) has no place in the z-line
+  // order: such a tile searches the whole adjacent rows in global memory
+  const bool stage = !__any(mine && !(fabsf(h.y) <= kMaxCoord));
+  const RowConst rc = d.rows[row];
+  const RowView dn = adjacent_view(d, sr - 1, zmin, zmax, rc.wz_dn, stage, lyz[0], lbs[0]);
+  const RowView up = adjacent_view(d, sr + 1, zmin, zmax, rc.wz_up, stage, lyz[1], lbs[1]);
   __syncthreads();
-  links_row(d, sr, dn, up, d.rows[row], rho, slots[threadIdx.x]);
+  if (mine) link_hit(d, p, h, dn, up, rc, rho, slots[lane]);
 }
 
 }  // namespace
 
-void launch_links(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s) {
-  if (d.SR == 0) return;
-  const uint32_t cap = max_row_hits < kLdsRowCap ? max_row_hits : kLdsRowCap;
-  const size_t lds = (size_t)(4 * cap + 2 * (cap + 2)) * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_links, dim3(d.SR), dim3(kThreads), lds, s, d, cap, d.rho);
+void launch_links(const DevPtrs& d, uint32_t, hipStream_t s) {
+  if (d.n_link_tiles == 0) return;
+  hipLaunchKernelGGL(k_links, dim3(d.n_link_tiles), dim3(kThreads), 0, s, d, d.rho);
 }
 
 }  // namespace tpc

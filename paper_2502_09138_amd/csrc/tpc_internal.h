@@ -6,8 +6,10 @@
 namespace tpc {
 
 constexpr int kMaxRows = 255;
+constexpr float kMaxCoord = 16384.0f;   // |y|, |z| beyond this (or non-finite) is flagged as bad input
 constexpr float kWinPad = 0.01f;    // cm added to a search window before binning (covers rounding)
 constexpr int kPasses = 6;
+constexpr uint32_t kLinkTile = 64;    // hits per K2 tile (one wave)
 
 // Per pad row: float32 constants used by C1, C2 and C5 (computed in double on the host, rounded once).
 struct RowConst {
@@ -74,6 +76,8 @@ struct DevPtrs {
   uint32_t* start_pos;       // [Tcap]
   uint32_t* start_sr;        // [Tcap]
   uint32_t* wave_off;        // [S+1] row-synchronous K5: first wave of each sector
+  const uint32_t* tile_off;  // [SR+1] K2: first tile of each row (ceil(N_r / kLinkTile) tiles per row)
+  uint32_t* tile_sr;         // [tiles] K2: row of each tile (written by K1)
   // C5
   int32_t* tk_rowhit;        // [R * Tcap]
   int32_t* tk_info;          // [4 * Tcap]: nHits, r_in, r_out, r0
@@ -105,6 +109,7 @@ struct DevPtrs {
   uint32_t S, R, SR, N;
   uint32_t tcap;
   uint32_t tile_cap;         // LDS words of one selector tile (max hits in a sector's row block)
+  uint32_t n_link_tiles;     // K2 tiles of this request
   uint32_t max_tracks;
   uint64_t max_track_clusters;
 };

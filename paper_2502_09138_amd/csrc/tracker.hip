@@ -42,7 +42,7 @@ constexpr uint32_t kSelectTileWords = 12288;   // 48 KB of LDS per selector tile
 
 struct Layout {   // byte offsets of every workspace buffer
   uint64_t row_off, rows, secs, row_dims, row_meta, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
-      row_start_off, start_pos, start_sr, wave_off, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, W, own_part, tk_pack,
+      row_start_off, start_pos, start_sr, wave_off, tile_off, tile_sr, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, W, own_part, tk_pack,
       tk_scan,
       out_sector, out_start, out_first, out_clusters, out_xref, out_param, out_cov, out_chi2, out_ndf, scan_blocks,
       hdr, in_y, in_z, total;
@@ -91,6 +91,8 @@ Layout layout_of(const Caps& k) {
   L.start_pos = take(k.T * 4);
   L.start_sr = take(k.T * 4);
   L.wave_off = take(((uint64_t)k.Smax + 1) * 4);
+  L.tile_off = take((k.SRmax + 1) * 4);
+  L.tile_sr = take((k.N / kLinkTile + k.SRmax + 1) * 4);   // sum of ceil(N_r / 64) <= N / 64 + SR
   L.tk_rowhit = take((uint64_t)k.R * k.T * 4);
   L.tk_info = take(4 * k.T * 4);
   L.tk_param = take(5 * k.T * 4);
@@ -161,6 +163,7 @@ struct tpc_tracker {
   std::vector<RowConst> rows;
   // pinned host memory
   uint32_t* h_row_off = nullptr;
+  uint32_t* h_tile_off = nullptr;
   SectorConst* h_secs = nullptr;
   ResultHeader* h_hdr = nullptr;
   char* h_out = nullptr;      // all outputs, laid out like the device outputs
@@ -320,6 +323,8 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   d.start_pos = (uint32_t*)(w + lay.start_pos);
   d.start_sr = (uint32_t*)(w + lay.start_sr);
   d.wave_off = (uint32_t*)(w + lay.wave_off);
+  d.tile_off = (const uint32_t*)(w + lay.tile_off);
+  d.tile_sr = (uint32_t*)(w + lay.tile_sr);
   d.tk_rowhit = (int32_t*)(w + lay.tk_rowhit);
   d.tk_info = (int32_t*)(w + lay.tk_info);
   d.tk_param = (float*)(w + lay.tk_param);
@@ -349,6 +354,7 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   d.max_track_clusters = caps.MC;
   // pinned host buffers
   if (hipHostMalloc((void**)&t->h_row_off, (caps.SRmax + 1) * 4) != hipSuccess ||
+      hipHostMalloc((void**)&t->h_tile_off, (caps.SRmax + 1) * 4) != hipSuccess ||
       hipHostMalloc((void**)&t->h_secs, caps.Smax * sizeof(SectorConst)) != hipSuccess ||
       hipHostMalloc((void**)&t->h_hdr, sizeof(ResultHeader)) != hipSuccess)
     return cleanup(fail(TPC_E_NOMEM, "hipHostMalloc staging"));
@@ -377,6 +383,7 @@ void tpc_tracker_destroy(tpc_tracker* t) {
     if (e) (void)hipEventDestroy(e);
   if (t->own_ws && t->ws) (void)hipFree(t->ws);
   if (t->h_row_off) (void)hipHostFree(t->h_row_off);
+  if (t->h_tile_off) (void)hipHostFree(t->h_tile_off);
   if (t->h_secs) (void)hipHostFree(t->h_secs);
   if (t->h_hdr) (void)hipHostFree(t->h_hdr);
   if (t->h_out) (void)hipHostFree(t->h_out);
@@ -463,6 +470,17 @@ tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t*
   } else {
     d.y = f->y;
     d.z = f->z;
+  }
+  // K2 tiles: ceil(N_r / kLinkTile) per row, first tile of each row
+  {
+    uint32_t nt = 0;
+    for (uint32_t i = 0; i < SR; ++i) {
+      t->h_tile_off[i] = nt;
+      nt += (f->row_offsets[i + 1] - f->row_offsets[i] + kLinkTile - 1) / kLinkTile;
+    }
+    t->h_tile_off[SR] = nt;
+    d.n_link_tiles = nt;
+    HIP_TRY(hipMemcpyAsync((void*)d.tile_off, t->h_tile_off, (SR + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st));
   }
   // selector tile: the most rows per tile (8, 4, 2, 1) whose largest sector row
   // block fits the LDS budget; 0 = rows too large, global-memory selector.

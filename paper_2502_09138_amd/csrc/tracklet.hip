@@ -204,7 +204,12 @@ __device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const R
 }
 
 // The same search over a row staged in LDS: (y, z) of the row's hits at
-// yz[q - first] and its bin starts (global positions) in bs[].
+// yz[q - first] and its bin starts (global positions) in bs[].  The candidate
+// loop reads four hits per trip (indices clamped to the z-line, so every read
+// stays in the staged row) and the next z-line's bounds are read before the
+// current line is scanned, so LDS latency is paid once per four candidates.
+// Candidates are still considered in ascending position, so ties resolve to
+// the smaller position exactly as in the global-memory search.
 __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* bs, uint32_t first, uint2 meta,
                                               const RowK& rk, const SectorConst& sc, const Trk& t, const KfConst& k,
                                               float zref) {
@@ -220,18 +225,28 @@ __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* 
   const int iz1 = bin1((za + wz) + kWinPad, sc.z_lo, sc.inv_wz, nz);
   int32_t best = -1;
   float bd = 0.0f;
+  uint32_t lo = bs[iz0 * ny + iy0], hi = bs[iz0 * ny + iy1 + 1];
   for (int iz = iz0; iz <= iz1; ++iz) {
-    const uint32_t lo = bs[iz * ny + iy0], hi = bs[iz * ny + iy1 + 1];
-    for (uint32_t q = lo; q < hi; ++q) {
-      const float2 h = yz[q - first];
-      const float dy = h.x - yp, dz = (h.y - zref) - zp;
-      if (!(fabsf(dy) <= wy && fabsf(dz) <= wz)) continue;
-      const float dd = dy * dy * isy + dz * dz * isz;
-      if (best < 0 || dd < bd) {
-        best = (int32_t)q;
-        bd = dd;
+    const int izn = min(iz + 1, iz1);
+    const uint32_t lo_n = bs[izn * ny + iy0], hi_n = bs[izn * ny + iy1 + 1];
+    for (uint32_t q = lo; q < hi; q += 4) {
+      float2 h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[j] = yz[min(q + j, hi - 1) - first];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float dy = h[j].x - yp, dz = (h[j].y - zref) - zp;
+        if (q + j < hi && fabsf(dy) <= wy && fabsf(dz) <= wz) {
+          const float dd = dy * dy * isy + dz * dz * isz;
+          if (best < 0 || dd < bd) {
+            best = (int32_t)(q + j);
+            bd = dd;
+          }
+        }
       }
     }
+    lo = lo_n;
+    hi = hi_n;
   }
   return best;
 }
@@ -490,49 +505,49 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
   return v;
 }
 
-// Issue the loads of row sr into registers (no LDS traffic yet).
-__device__ __forceinline__ void prefetch_row(const DevPtrs& d, uint32_t sr, Prefetch& pf) {
+// Issue the loads of sector row r (wave-uniform) into registers.  The row's
+// offsets and grid word come from the wave's LDS copy of the sector's row
+// table, so no load here waits on another; every lane loads from an index
+// clamped into the row, so the loads need no per-lane predication.
+__device__ __forceinline__ void prefetch_row(const DevPtrs& d, const uint32_t* roff_s, const uint2* meta_s, uint32_t r,
+                                             Prefetch& pf) {
   const uint32_t lane = threadIdx.x;
-  pf.st.first = d.row_off[sr];
-  pf.st.n = d.row_off[sr + 1] - pf.st.first;
-  pf.st.meta = d.row_meta[sr];
+  pf.st.first = roff_s[r];
+  pf.st.n = roff_s[r + 1] - pf.st.first;
+  pf.st.meta = meta_s[r];
   pf.st.fits = pf.st.n <= (uint32_t)kStageHits;
   if (!pf.st.fits) return;
-  const uint32_t nb1 = (pf.st.meta.y & 0xFFFFu) * (pf.st.meta.y >> 16) + 1;
+  if (pf.st.n > 0) {
+    const uint32_t last = pf.st.first + pf.st.n - 1;
 #pragma unroll
-  for (int m = 0; m < kPreYz; ++m) {
-    const uint32_t j = lane + m * kThreads;
-    if (j < pf.st.n) pf.yz[m] = d.syz[pf.st.first + j];
+    for (int m = 0; m < kPreYz; ++m) pf.yz[m] = d.syz[min(pf.st.first + lane + m * kThreads, last)];
   }
+  const uint32_t nb1 = (pf.st.meta.y & 0xFFFFu) * (pf.st.meta.y >> 16) + 1;   // >= 2: every row has a grid
+  const uint32_t blast = pf.st.meta.x + nb1 - 1;
 #pragma unroll
-  for (int m = 0; m < kPreBs; ++m) {
-    const uint32_t j = lane + m * kThreads;
-    if (j < nb1) pf.bs[m] = d.bin_start[pf.st.meta.x + j];
-  }
+  for (int m = 0; m < kPreBs; ++m) pf.bs[m] = d.bin_start[min(pf.st.meta.x + lane + m * kThreads, blast)];
 }
 
 // Write prefetched registers to the LDS stage (call between two barriers).
+// Slots past the row's end receive copies of its last entries and are never read.
 __device__ __forceinline__ void commit_row(const Prefetch& pf, float2* yz_s, uint32_t* bs_s, Stage& st) {
   const uint32_t lane = threadIdx.x;
   st = pf.st;
   if (!st.fits) return;
-  const uint32_t nb1 = (st.meta.y & 0xFFFFu) * (st.meta.y >> 16) + 1;
+  if (st.n > 0) {
 #pragma unroll
-  for (int m = 0; m < kPreYz; ++m) {
-    const uint32_t j = lane + m * kThreads;
-    if (j < st.n) yz_s[j] = pf.yz[m];
+    for (int m = 0; m < kPreYz; ++m) yz_s[lane + m * kThreads] = pf.yz[m];
   }
 #pragma unroll
-  for (int m = 0; m < kPreBs; ++m) {
-    const uint32_t j = lane + m * kThreads;
-    if (j < nb1) bs_s[j] = pf.bs[m];
-  }
+  for (int m = 0; m < kPreBs; ++m) bs_s[lane + m * kThreads] = pf.bs[m];
 }
 
 __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k) {
   __shared__ RowK lrows[kMaxRows];
-  __shared__ float2 yz_s[kStageHits];
-  __shared__ uint32_t bs_s[kStageBins];
+  __shared__ float2 yz_s[kPreYz * kThreads];     // >= kStageHits
+  __shared__ uint32_t bs_s[kPreBs * kThreads];   // >= kStageBins
+  __shared__ uint32_t roff_s[kMaxRows + 1];   // the current sector's row offsets
+  __shared__ uint2 meta_s[kMaxRows];          // and grid words
   load_rows(d, lrows);
   const uint32_t R = d.R, T = d.tcap, S = d.S;
   const uint32_t lane = threadIdx.x;
@@ -554,6 +569,12 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
     const uint32_t i = ts + (v - d.wave_off[sec]) * kThreads + lane;
     const SectorConst sc = d.secs[sec];
     int32_t* H = d.tk_rowhit + i;
+    __syncthreads();   // the previous wave's last reads of the row table are done
+    for (uint32_t q = lane; q <= R; q += kThreads) {
+      roff_s[q] = d.row_off[srb + q];
+      if (q < R) meta_s[q] = d.row_meta[srb + q];
+    }
+    __syncthreads();
     // ---- per lane: chain walk and seed ----
     bool ok = i < te;
     uint32_t r0 = 0, rl = 0, n = 0;
@@ -593,15 +614,15 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
     int miss = 0;
     Stage st;
     Prefetch pf;
-    uint32_t r = wave_min(up ? r0 + 1 : R);
+    uint32_t r = __builtin_amdgcn_readfirstlane(wave_min(up ? r0 + 1 : R));   // wave-uniform from here on
     if (r < R) {
-      prefetch_row(d, srb + r, pf);
+      prefetch_row(d, roff_s, meta_s, r, pf);
       commit_row(pf, yz_s, bs_s, st);
       __syncthreads();
     }
     int32_t hnext = (up && r <= rl && r > r0) ? H[(size_t)r * T] : -1;
     while (r < R && __any(up)) {
-      if (r + 1 < R) prefetch_row(d, srb + r + 1, pf);
+      if (r + 1 < R) prefetch_row(d, roff_s, meta_s, r + 1, pf);
       const int32_t hchain = hnext;
       hnext = (up && r + 1 <= rl && r + 1 > r0) ? H[(size_t)(r + 1) * T] : -1;
       if (up && r > r0) {
@@ -663,15 +684,15 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
       xprev = lrows[rout].x;
       miss = 0;
     }
-    int32_t rr = (int32_t)wave_max(down ? rout : 0) - 1;
+    int32_t rr = (int32_t)__builtin_amdgcn_readfirstlane(wave_max(down ? rout : 0)) - 1;
     if (rr >= 0) {
-      prefetch_row(d, srb + (uint32_t)rr, pf);
+      prefetch_row(d, roff_s, meta_s, (uint32_t)rr, pf);
       commit_row(pf, yz_s, bs_s, st);
       __syncthreads();
     }
     hnext = (down && rr >= (int32_t)r0 && rr < (int32_t)rout) ? H[(size_t)rr * T] : -1;
     while (rr >= 0 && __any(down)) {
-      if (rr > 0) prefetch_row(d, srb + (uint32_t)rr - 1, pf);
+      if (rr > 0) prefetch_row(d, roff_s, meta_s, (uint32_t)rr - 1, pf);
       const int32_t hrow = hnext;
       hnext = (down && rr - 1 >= (int32_t)r0 && rr - 1 < (int32_t)rout) ? H[(size_t)(rr - 1) * T] : -1;
       if (down && rr < (int32_t)rout) {
