@@ -170,7 +170,11 @@ __device__ __forceinline__ void set_c0(Trk& t, const KfConst& k) {
   t.c[tri(4, 4)] = k.c0_qpt;
 }
 
-// Grid search in row sr for the candidate closest to (yp, zp); -1 if none.
+// Grid search in row sr for the candidate closest to the prediction; -1 if
+// none.  z-lines are walked as one flat sequence of candidate groups per lane
+// (see search_lds); the kGroup loads of a group are issued together.
+constexpr int kGroup = 4;
+
 __device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const RowK& rk, const SectorConst& sc,
                                           const Trk& t, const KfConst& k, float zref) {
   const uint2 meta = d.row_meta[sr];
@@ -187,29 +191,44 @@ __device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const R
   const uint32_t* bs = d.bin_start + meta.x;
   int32_t best = -1;
   float bd = 0.0f;
-  for (int iz = iz0; iz <= iz1; ++iz) {
-    const uint32_t lo = bs[iz * ny + iy0], hi = bs[iz * ny + iy1 + 1];
-    for (uint32_t q = lo; q < hi; ++q) {
-      const float2 h = d.syz[q];
-      const float dy = h.x - yp, dz = (h.y - zref) - zp;
-      if (!(fabsf(dy) <= wy && fabsf(dz) <= wz)) continue;
-      const float dd = dy * dy * isy + dz * dz * isz;
-      if (best < 0 || dd < bd) {
-        best = (int32_t)q;
-        bd = dd;
+  int iz = iz0;
+  uint32_t q = bs[iz * ny + iy0], hi = bs[iz * ny + iy1 + 1];
+  for (;;) {
+    while (q >= hi && iz < iz1) {
+      ++iz;
+      q = bs[iz * ny + iy0];
+      hi = bs[iz * ny + iy1 + 1];
+    }
+    if (q >= hi) break;
+    float2 h[kGroup];
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) h[j] = d.syz[min(q + j, hi - 1)];
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) {
+      const float dy = h[j].x - yp, dz = (h[j].y - zref) - zp;
+      if (q + j < hi && fabsf(dy) <= wy && fabsf(dz) <= wz) {
+        const float dd = dy * dy * isy + dz * dz * isz;
+        if (best < 0 || dd < bd) {
+          best = (int32_t)(q + j);
+          bd = dd;
+        }
       }
     }
+    q += kGroup;
   }
   return best;
 }
 
 // The same search over a row staged in LDS: (y, z) of the row's hits at
-// yz[q - first] and its bin starts (global positions) in bs[].  The candidate
-// loop reads four hits per trip (indices clamped to the z-line, so every read
-// stays in the staged row) and the next z-line's bounds are read before the
-// current line is scanned, so LDS latency is paid once per four candidates.
-// Candidates are still considered in ascending position, so ties resolve to
-// the smaller position exactly as in the global-memory search.
+// yz[q - first] and its bin starts (global positions) in bs[].  Each lane walks
+// its z-lines as one flat sequence of candidate groups (a lane moves to its
+// next z-line as soon as the current one is exhausted), so a wave runs for the
+// largest per-lane candidate count rather than the sum over z-lines of the
+// per-line maxima.  A group reads kGroup hits at once (indices clamped to the
+// z-line, so every read stays in the staged row).  Candidates are considered in
+// ascending position, so ties resolve to the smaller position exactly as in the
+// global-memory search.
+
 __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* bs, uint32_t first, uint2 meta,
                                               const RowK& rk, const SectorConst& sc, const Trk& t, const KfConst& k,
                                               float zref) {
@@ -225,28 +244,30 @@ __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* 
   const int iz1 = bin1((za + wz) + kWinPad, sc.z_lo, sc.inv_wz, nz);
   int32_t best = -1;
   float bd = 0.0f;
-  uint32_t lo = bs[iz0 * ny + iy0], hi = bs[iz0 * ny + iy1 + 1];
-  for (int iz = iz0; iz <= iz1; ++iz) {
-    const int izn = min(iz + 1, iz1);
-    const uint32_t lo_n = bs[izn * ny + iy0], hi_n = bs[izn * ny + iy1 + 1];
-    for (uint32_t q = lo; q < hi; q += 4) {
-      float2 h[4];
+  int iz = iz0;
+  uint32_t q = bs[iz * ny + iy0], hi = bs[iz * ny + iy1 + 1];
+  for (;;) {
+    while (q >= hi && iz < iz1) {
+      ++iz;
+      q = bs[iz * ny + iy0];
+      hi = bs[iz * ny + iy1 + 1];
+    }
+    if (q >= hi) break;
+    float2 h[kGroup];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) h[j] = yz[min(q + j, hi - 1) - first];
+    for (int j = 0; j < kGroup; ++j) h[j] = yz[min(q + j, hi - 1) - first];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float dy = h[j].x - yp, dz = (h[j].y - zref) - zp;
-        if (q + j < hi && fabsf(dy) <= wy && fabsf(dz) <= wz) {
-          const float dd = dy * dy * isy + dz * dz * isz;
-          if (best < 0 || dd < bd) {
-            best = (int32_t)(q + j);
-            bd = dd;
-          }
+    for (int j = 0; j < kGroup; ++j) {
+      const float dy = h[j].x - yp, dz = (h[j].y - zref) - zp;
+      if (q + j < hi && fabsf(dy) <= wy && fabsf(dz) <= wz) {
+        const float dd = dy * dy * isy + dz * dz * isz;
+        if (best < 0 || dd < bd) {
+          best = (int32_t)(q + j);
+          bd = dd;
         }
       }
     }
-    lo = lo_n;
-    hi = hi_n;
+    q += kGroup;
   }
   return best;
 }
