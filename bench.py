@@ -71,6 +71,40 @@ def cpu_baseline(ev, budget_s):
                        f"one thread, {t_total:.1f} s", seconds=t_total)
 
 
+def serve_main(args):
+    """Plain path (one slot, FIFO) versus served path (several slots) on the same trace."""
+    import torch
+    from paper_2502_09138_amd import serving
+    dev = torch.device("cuda", 0)
+    log("serve: generating the frame pool")
+    pool = serving.make_pool(dev, log=log)
+    trace = serving.make_trace(pool, rate_hz=args.rate, duration_s=args.serve, seed=5)
+    cap = max(f.n_clusters for f in pool)
+    res = {}
+    for label, slots in (("plain", 1), ("served", args.slots)):
+        srv = serving.Server(max_clusters=cap, slots=slots)
+        srv.run(pool, trace[:min(20, len(trace))])           # warm-up on the head of the trace
+        log(f"serve: {label} with {srv.slots} slot(s), {len(trace)} requests over {args.serve} s")
+        rec, _, wall = srv.run(pool, trace)
+        res[label] = dict(serving.summarize(rec, wall, args.serve), slots=srv.slots)
+        srv.close()
+        log(f"serve: {label}: {res[label]}")
+    out = {
+        "metric": "p50/p99 time-frame latency, plain vs served, Poisson trace",
+        "value": round(res["served"]["p99_ms"], 3),
+        "unit": "ms (p99, served)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "data": "synthetic",
+        "dtype": "f32",
+        "config": {"workload": "poisson_trace", "rate_hz": args.rate, "duration_s": args.serve,
+                   "pp_fraction": 0.8, "pool": [f"{f.name}:{f.n_clusters}" for f in pool]},
+        "plain": res["plain"],
+        "served": res["served"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,15 +115,28 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", type=int, default=0,
                     help="tracklet kernel schedule: 0 auto, 1 per-lane gathers, 2 row-synchronous LDS stage")
+    ap.add_argument("--mode", choices=("batched", "per_sector"), default="batched",
+                    help="batched: one request per frame (default); per_sector: one request per sector, the plain "
+                         "baseline the batched path is compared with")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this size first (PMC byte-counter calibration)")
+    ap.add_argument("--serve", type=float, default=0.0,
+                    help="instead of the plain bench: serve a Poisson trace of this many seconds with one slot (plain "
+                         "path) and with --slots slots, report p50/p99 latency and clusters/s of both")
+    ap.add_argument("--slots", type=int, default=3)
+    ap.add_argument("--rate", type=float, default=200.0, help="trace arrival rate (requests/s) for --serve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sectors and time frames "
               "shard across GPUs with no exchange, so the per-GPU figure is the one reported)", file=sys.stderr)
         sys.exit(2)
 
+    if args.serve > 0:
+        serve_main(args)
+        return
+
     import torch
+    from paper_2502_09138_amd import batching
     from paper_2502_09138_amd.config import default_config
     from paper_2502_09138_amd.tracker import Tracker
 
@@ -111,12 +158,30 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    def step():
+    def step_batched():
         rid = tr.submit(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
         counts = tr.get_device(rid)
         passes = tr.pass_times()
         tr.release(rid)
         return counts, passes
+
+    spans = batching.sector_spans(ev.row_offsets)
+    zlo = np.asarray(ev.sector_z_lo, np.float32)
+    zhi = np.asarray(ev.sector_z_hi, np.float32)
+
+    def step_per_sector():
+        counts, passes = {"n_tracks": 0, "n_tracklets": 0, "n_steps": 0}, {}
+        for s, a, b, ro in spans:
+            rid = tr.submit(y[a:b], z[a:b], ro, zlo[s:s + 1], zhi[s:s + 1])
+            c = tr.get_device(rid)
+            for k, v in tr.pass_times().items():
+                passes[k] = passes.get(k, 0.0) + v
+            tr.release(rid)
+            for k in counts:
+                counts[k] += c[k]
+        return counts, passes
+
+    step = step_batched if args.mode == "batched" else step_per_sector
 
     for _ in range(args.warmup):
         step()
@@ -136,9 +201,10 @@ def main():
     n_e2e = max(3, args.steps // 2)
     t1 = time.perf_counter()
     for _ in range(n_e2e):
-        rid = tr.submit(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
-        out = tr.get(rid)
-        tr.release(rid)
+        if args.mode == "batched":
+            out = tr.track(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+        else:
+            out = batching.track_per_sector(tr, y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
     e2e = time.perf_counter() - t1
     assert out.n_tracks == counts["n_tracks"]
 
@@ -172,7 +238,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": dict(wl, n_clusters=N, n_sectors=ev.n_sectors, n_rows=152, tracklets=counts["n_tracklets"],
-                       tracks=counts["n_tracks"], tracklet_schedule=args.schedule),
+                       tracks=counts["n_tracks"], tracklet_schedule=args.schedule, mode=args.mode),
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 4),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 4)},
         "e2e_host_copy": {"value": round(N * n_e2e / e2e, 1), "unit": "clusters/s",

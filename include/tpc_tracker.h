@@ -251,6 +251,14 @@ enum {
  * *bytes receives the full size.  Waits for the request. */
 tpc_status tpc_debug_copy(tpc_tracker* t, int32_t what, void* host_dst, uint64_t cap_bytes, uint64_t* bytes);
 
+/* Selects the tracklet-constructor schedule for later requests (same meaning
+ * as tpc_tracker_config.tracklet_schedule: 0 auto, 1 one lane per tracklet with
+ * global-memory searches, 2 row-synchronous waves with LDS-staged rows).  All
+ * schedules compute the same step C5; they differ in memory traffic and
+ * speed, which is what a shape-class autotuner chooses between.  Returns
+ * TPC_E_INVAL for other values or while a request is in flight. */
+tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule);
+
 /* Per-pass timing with HIP events on the tracker's stream. */
 #define TPC_N_PASSES 6     /* K1 grid, K2 neighbours, K3/K4 clean+starts, K5 tracklets, K6 select, output */
 tpc_status tpc_set_timing(tpc_tracker* t, int32_t enable);

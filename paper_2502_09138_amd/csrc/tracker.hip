@@ -652,6 +652,15 @@ tpc_status tpc_debug_copy(tpc_tracker* t, int32_t what, void* dst, uint64_t cap,
   return TPC_OK;
 }
 
+tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule) {
+  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
+  if (schedule < 0 || schedule > 2) return fail(TPC_E_INVAL, "tracklet_schedule must be 0, 1 or 2");
+  if (t->in_flight) return fail(TPC_E_INVAL, "a request is in flight");
+  t->cfg.tracklet_schedule = schedule;
+  t->d.k5_mode = schedule;
+  return TPC_OK;
+}
+
 tpc_status tpc_set_timing(tpc_tracker* t, int32_t enable) {
   if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
   t->timing = enable != 0;

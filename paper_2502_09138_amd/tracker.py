@@ -76,7 +76,7 @@ class _Tracks(C.Structure):
 
 EXPORTED = ("tpc_default_config", "tpc_workspace_bytes", "tpc_tracker_create", "tpc_tracker_destroy",
             "tpc_track_timeframe", "tpc_get_tracks", "tpc_get_tracks_device", "tpc_release", "tpc_last_error", "tpc_debug_copy",
-            "tpc_set_timing", "tpc_get_pass_times")
+            "tpc_set_timing", "tpc_get_pass_times", "tpc_set_tracklet_schedule")
 
 _lib = None
 
@@ -108,6 +108,8 @@ def load():
     L.tpc_last_error.restype = C.c_char_p
     L.tpc_debug_copy.restype = C.c_int32
     L.tpc_debug_copy.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint64, P(C.c_uint64)]
+    L.tpc_set_tracklet_schedule.restype = C.c_int32
+    L.tpc_set_tracklet_schedule.argtypes = [C.c_void_p, C.c_int32]
     L.tpc_set_timing.restype = C.c_int32
     L.tpc_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.tpc_get_pass_times.restype = C.c_int32
@@ -302,6 +304,10 @@ class Tracker:
         if n.value:
             _check(L.tpc_debug_copy(self._h, what, out.ctypes.data, n.value, C.byref(n)))
         return out
+
+    def set_tracklet_schedule(self, schedule):
+        """0 auto, 1 one lane per tracklet, 2 row-synchronous (applies to later requests)."""
+        _check(load().tpc_set_tracklet_schedule(self._h, int(schedule)))
 
     def set_timing(self, on=True):
         _check(load().tpc_set_timing(self._h, 1 if on else 0))

@@ -75,3 +75,4 @@ def test_null_arguments_rejected(lib):
     assert lib.tpc_tracker_create(None, None) == trk.TPC_E_INVAL
     assert lib.tpc_track_timeframe(None, None, None) == trk.TPC_E_INVAL
     assert lib.tpc_release(None, 1) == trk.TPC_E_INVAL
+    assert lib.tpc_set_tracklet_schedule(None, 1) == trk.TPC_E_INVAL
