@@ -32,6 +32,10 @@ namespace tpc {
 namespace {
 
 constexpr int kThreads = 64;
+// Row-synchronous schedule: two lanes per tracklet (the pair splits the
+// candidate search and runs the rest of the step redundantly).
+constexpr int kPair = 2;
+constexpr int kTrkPerWave = kThreads / kPair;
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }   // i >= j
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -220,18 +224,15 @@ __device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const R
 }
 
 // The same search over a row staged in LDS: (y, z) of the row's hits at
-// yz[q - first] and its bin starts (global positions) in bs[].  Each lane walks
-// its z-lines as one flat sequence of candidate groups (a lane moves to its
-// next z-line as soon as the current one is exhausted), so a wave runs for the
-// largest per-lane candidate count rather than the sum over z-lines of the
-// per-line maxima.  A group reads kGroup hits at once (indices clamped to the
-// z-line, so every read stays in the staged row).  Candidates are considered in
-// ascending position, so ties resolve to the smaller position exactly as in the
-// global-memory search.
-
+// yz[q - first] and its bin starts (global positions) in bs[].  It is run by the
+// two lanes of a pair that carry the same tracklet: on every z-line they take
+// alternate groups of kGroup candidates (indices clamped to the z-line, so every
+// read stays in the staged row), walking the z-lines as one flat sequence, and
+// then exchange their best candidates.  The result -- smallest deviation, ties
+// to the smaller position -- is the same as a single ascending scan.
 __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* bs, uint32_t first, uint2 meta,
                                               const RowK& rk, const SectorConst& sc, const Trk& t, const KfConst& k,
-                                              float zref) {
+                                              float zref, uint32_t half) {
   const float sy2 = t.c[0] + k.vy, sz2 = t.c[2] + k.vz;
   const float wy = fminf(k.gate * fsqrt(sy2), k.cap), wz = fminf(k.gate * fsqrt(sz2), k.cap);
   const float isy = frcp(sy2), isz = frcp(sz2);
@@ -244,12 +245,13 @@ __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* 
   const int iz1 = bin1((za + wz) + kWinPad, sc.z_lo, sc.inv_wz, nz);
   int32_t best = -1;
   float bd = 0.0f;
+  // the two lanes of a pair take alternate groups of every z-line
   int iz = iz0;
-  uint32_t q = bs[iz * ny + iy0], hi = bs[iz * ny + iy1 + 1];
+  uint32_t q = bs[iz * ny + iy0] + half * kGroup, hi = bs[iz * ny + iy1 + 1];
   for (;;) {
     while (q >= hi && iz < iz1) {
       ++iz;
-      q = bs[iz * ny + iy0];
+      q = bs[iz * ny + iy0] + half * kGroup;
       hi = bs[iz * ny + iy1 + 1];
     }
     if (q >= hi) break;
@@ -267,7 +269,14 @@ __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* 
         }
       }
     }
-    q += kGroup;
+    q += kPair * kGroup;
+  }
+  // the pair's two candidates: smaller deviation, ties to the smaller position
+  const int32_t ob = __shfl_xor(best, 1, kWave);
+  const float od = __shfl_xor(bd, 1, kWave);
+  if (ob >= 0 && (best < 0 || od < bd || (od == bd && ob < best))) {
+    best = ob;
+    bd = od;
   }
   return best;
 }
@@ -490,8 +499,12 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
 
 // ---------------------------------------------------------------------------
 // Row-synchronous schedule ("coalesced row-grid reads").  A wave takes up to
-// 64 tracklets of ONE sector.  After each lane has walked its chain and built
-// its seed, the wave sweeps the rows in lockstep -- outward, then inward --
+// 32 tracklets of ONE sector, two lanes per tracklet: the pair splits each
+// candidate search and runs the rest of the step redundantly, which shortens
+// the wave's per-row instruction stream (a wave's critical path, not the SIMD's
+// throughput, bounds this kernel: about one wave per SIMD is resident).  After
+// each pair has walked its chain and built its seed, the wave sweeps the rows
+// in lockstep -- outward, then inward --
 // and at every row stages that row's (y, z) and bin starts in LDS with one
 // coalesced load shared by all lanes; the loads for the next row are issued
 // before the current row's Kalman step and land in registers while it runs.
@@ -587,7 +600,8 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
     }
     const uint32_t sec = lo, srb = sec * R;
     const uint32_t ts = min(d.row_start_off[srb], T), te = min(d.row_start_off[srb + R], T);
-    const uint32_t i = ts + (v - d.wave_off[sec]) * kThreads + lane;
+    const uint32_t half = lane & 1u;   // both lanes of a pair compute the same tracklet and store identical values
+    const uint32_t i = ts + (v - d.wave_off[sec]) * kTrkPerWave + (lane >> 1);
     const SectorConst sc = d.secs[sec];
     int32_t* H = d.tk_rowhit + i;
     __syncthreads();   // the previous wave's last reads of the row table are done
@@ -660,7 +674,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
           } else {
             int32_t h = hchain;
             if (!chain) {
-              h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref)
+              h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
                           : search(d, srb + r, rk, sc, t, k, zref);
               H[(size_t)r * T] = h;
             }
@@ -729,7 +743,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
           } else {
             int32_t h = below ? -1 : hrow;
             if (h < 0)
-              h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref)
+              h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
                           : search(d, srb + (uint32_t)rr, rk, sc, t, k, zref);
             H[(size_t)rr * T] = h;
             if (h >= 0) {
@@ -752,13 +766,13 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
     }
     if (ok) {
       store_tracklet(d, i, nh, rin, rout, r0, snap, chi2, zref);
-      my_steps += steps;
+      if (half == 0) my_steps += steps;
     }
   }
   if (my_steps) atomicAdd(&d.hdr->n_steps, my_steps);
 }
 
-// Waves of the row-synchronous schedule: ceil(tracklets of sector s / 64) per
+// Waves of the row-synchronous schedule: ceil(tracklets of sector s / 32) per
 // sector, prefix-summed (one block).
 __global__ void __launch_bounds__(1024) k_waves(DevPtrs d) {
   __shared__ uint32_t wsum[1024 / kWave];
@@ -768,14 +782,14 @@ __global__ void __launch_bounds__(1024) k_waves(DevPtrs d) {
   uint32_t sum = 0;
   for (uint32_t s = s0; s < s1; ++s) {
     const uint32_t a = min(d.row_start_off[s * R], T), b = min(d.row_start_off[(s + 1) * R], T);
-    sum += (b - a + kThreads - 1) / kThreads;
+    sum += (b - a + kTrkPerWave - 1) / kTrkPerWave;
   }
   uint32_t total;
   uint32_t run = block_exclusive_scan<uint32_t>(sum, wsum, &total);
   for (uint32_t s = s0; s < s1; ++s) {
     d.wave_off[s] = run;
     const uint32_t a = min(d.row_start_off[s * R], T), b = min(d.row_start_off[(s + 1) * R], T);
-    run += (b - a + kThreads - 1) / kThreads;
+    run += (b - a + kTrkPerWave - 1) / kTrkPerWave;
   }
   if (threadIdx.x == 0) d.wave_off[S] = total;
 }
@@ -787,7 +801,7 @@ void launch_tracklets(const DevPtrs& d, const KfConst& k, uint32_t max_row_hits,
   const bool rowsync = d.k5_mode == 2 || (d.k5_mode == 0 && max_row_hits <= (uint32_t)kStageHits);
   if (rowsync) {
     hipLaunchKernelGGL(k_waves, dim3(1), dim3(1024), 0, s, d);
-    uint32_t blocks = (d.tcap + kThreads - 1) / kThreads + d.S;
+    uint32_t blocks = (d.tcap + kTrkPerWave - 1) / kTrkPerWave + d.S;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_tracklets_rs, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
     return;
