@@ -32,6 +32,34 @@ K1_BYTES_PER_CLUSTER = 22.0     # read y, z; write sorted (y, z), id, ~2 B of bi
 K2_BYTES_PER_CLUSTER = 18.0     # read own (y, z) + each adjacent row once + bin starts; write up0/down0
 
 
+# HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scaled on a 1 GiB device copy) from two
+# rocprofv3 --pmc passes of this script (commands and tables in profiles/), valid for the kernel sources
+# with these SHA-1 digests; reported as null once a source differs.
+PMC_SOURCES = {
+    "paper_2502_09138_amd/csrc/tracklet.hip": "89a06232437fe824b68ad6ab6805cb1d57682f6b",
+    "paper_2502_09138_amd/csrc/links.hip": "2bfbb985539bfef883dc0bb3b2252c98c43531d0",
+    "paper_2502_09138_amd/csrc/grid.hip": "6460655febd2a7f572bd7741e338bdc971bf3f8e",
+    "paper_2502_09138_amd/csrc/device_common.h": "b4b103e57db5db269528a9bdae40217f2bb52ff1",
+    "paper_2502_09138_amd/csrc/tpc_internal.h": "da359e63a52ba9731d81e2297cf6afec2fee1145",
+}
+MIB = float(1 << 20)
+PMC_TRAFFIC = {   # workload -> pass -> (fetch MiB, write MiB) per launch
+    "central_event": {"tracklets": (65.82, 89.60), "grid": (11.69, 18.10), "neighbours": (40.58, 10.98)},
+    "time_frame": {"tracklets": (7299.42, 1842.24), "grid": (84.84, 135.87), "neighbours": (367.29, 84.48)},
+    "uneven_chunks": {"tracklets": (11214.40, 5490.11), "grid": (167.15, 260.15), "neighbours": (828.83, 158.48)},
+}
+
+
+def pmc_traffic(workload, pass_name):
+    import hashlib
+    for rel, digest in PMC_SOURCES.items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha1(f.read()).hexdigest() != digest:
+                return None
+    fw = PMC_TRAFFIC.get(workload, {}).get(pass_name)
+    return None if fw is None else round((fw[0] + fw[1]) * MIB)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -69,6 +97,13 @@ def cpu_baseline(ev, budget_s):
     return dict(value=done_clusters / t_total, unit="clusters/s", cores=1, kind="oracle",
                 sample=f"sectors 0..{sectors[-1]} of the workload ({done_clusters} clusters), full C1-C7, "
                        f"one thread, {t_total:.1f} s", seconds=t_total)
+
+
+def tr_schedule_rowsync(schedule, ev):
+    """Which K5 kernel runs: the row-synchronous one when forced, or in auto mode when every row fits its stage."""
+    if schedule in (1, 2):
+        return schedule == 2
+    return int(np.diff(np.asarray(ev.row_offsets, np.int64)).max()) <= 320
 
 
 def serve_main(args):
@@ -215,14 +250,19 @@ def main():
     k5_gbs = k5_bytes / (pass_ms["tracklets"] * 1e-3) / 1e9
     k1_gbs = K1_BYTES_PER_CLUSTER * N / (pass_ms["grid"] * 1e-3) / 1e9
     k2_gbs = K2_BYTES_PER_CLUSTER * N / (pass_ms["neighbours"] * 1e-3) / 1e9
+    k5_name = "k_tracklets_rs (K5, C5)" if tr_schedule_rowsync(args.schedule, ev) else "k_tracklets (K5, C5)"
     roof = {
-        "tracklets": dict(kernel="k_tracklets (K5, C5)", bound="hbm", achieved=round(k5_gbs, 2), peak=HBM_PEAK_GBS,
-                          unit="GB/s", frac=round(k5_gbs / HBM_PEAK_GBS, 5), traffic=None,
-                          note="latency-bound dependent gathers; bytes = 30 B/row step + 700 B/tracklet"),
+        "tracklets": dict(kernel=k5_name, bound="hbm", achieved=round(k5_gbs, 2), peak=HBM_PEAK_GBS,
+                          unit="GB/s", frac=round(k5_gbs / HBM_PEAK_GBS, 5), traffic=pmc_traffic(wl["workload"], "tracklets"),
+                          algorithmic_bytes=round(k5_bytes), kernel_ms=round(pass_ms["tracklets"], 4),
+                          note="latency-bound dependent row steps; bytes = 30 B/row step + 700 B/tracklet"),
         "grid": dict(kernel="k_grid_lds (K1, C1)", bound="hbm", achieved=round(k1_gbs, 2), peak=HBM_PEAK_GBS,
-                     unit="GB/s", frac=round(k1_gbs / HBM_PEAK_GBS, 5), traffic=None),
+                     unit="GB/s", frac=round(k1_gbs / HBM_PEAK_GBS, 5), traffic=pmc_traffic(wl["workload"], "grid"),
+                     algorithmic_bytes=round(K1_BYTES_PER_CLUSTER * N), kernel_ms=round(pass_ms["grid"], 4)),
         "neighbours": dict(kernel="k_links (K2, C2)", bound="hbm", achieved=round(k2_gbs, 2), peak=HBM_PEAK_GBS,
-                           unit="GB/s", frac=round(k2_gbs / HBM_PEAK_GBS, 5), traffic=None),
+                           unit="GB/s", frac=round(k2_gbs / HBM_PEAK_GBS, 5),
+                           traffic=pmc_traffic(wl["workload"], "neighbours"),
+                           algorithmic_bytes=round(K2_BYTES_PER_CLUSTER * N), kernel_ms=round(pass_ms["neighbours"], 4)),
     }
     rec = {
         "metric": "TPC clusters/s tracked at 1 GPU (plain path) + p50/p99 time-frame latency",
