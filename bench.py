@@ -79,24 +79,26 @@ def make_workload(name):
 
 
 def cpu_baseline(ev, budget_s):
-    """FP64 oracle, single thread, on whole sectors until ~budget_s of CPU work."""
+    """FP64 oracle, single thread, on whole sectors (cycling through the workload) until ~budget_s of CPU work."""
     from oracle import oracle
     from paper_2502_09138_amd.config import default_config
     cfg = default_config().as_dict()
-    R = 152
-    done_clusters, t_total, sectors = 0, 0.0, []
-    for s in range(ev.n_sectors):
-        sub = ev.sector_slice([s])
+    subs = []
+    done_clusters, t_total, n_runs = 0, 0.0, 0
+    while t_total < budget_s:
+        s = n_runs % ev.n_sectors
+        if len(subs) <= s:
+            subs.append(ev.sector_slice([s]))
+        sub = subs[s]
         t0 = time.perf_counter()
         oracle.Run.from_event(cfg, sub).run_all()
         t_total += time.perf_counter() - t0
         done_clusters += sub.n_clusters
-        sectors.append(s)
-        if t_total >= budget_s:
-            break
+        n_runs += 1
+    passes = n_runs / ev.n_sectors
     return dict(value=done_clusters / t_total, unit="clusters/s", cores=1, kind="oracle",
-                sample=f"sectors 0..{sectors[-1]} of the workload ({done_clusters} clusters), full C1-C7, "
-                       f"one thread, {t_total:.1f} s", seconds=t_total)
+                sample=f"{n_runs} whole-sector runs ({passes:.2f} passes over the workload's {ev.n_sectors} sectors, "
+                       f"{done_clusters} clusters), full C1-C7, one thread, {t_total:.1f} s", seconds=t_total)
 
 
 def tr_schedule_rowsync(schedule, ev):
