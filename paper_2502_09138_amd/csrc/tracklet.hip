@@ -541,25 +541,30 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 
 // Issue the loads of sector row r (wave-uniform) into registers.  The row's
 // offsets and grid word come from the wave's LDS copy of the sector's row
-// table, so no load here waits on another; every lane loads from an index
-// clamped into the row, so the loads need no per-lane predication.
+// table, so no load here waits on another; only the 64-entry chunks the row
+// needs are loaded (a scalar decision), each lane from an index clamped into
+// the row, so the loads need no per-lane predication.
 __device__ __forceinline__ void prefetch_row(const DevPtrs& d, const uint32_t* roff_s, const uint2* meta_s, uint32_t r,
                                              Prefetch& pf) {
   const uint32_t lane = threadIdx.x;
-  pf.st.first = roff_s[r];
-  pf.st.n = roff_s[r + 1] - pf.st.first;
-  pf.st.meta = meta_s[r];
+  // wave-uniform row facts, so that the load count below is a scalar decision
+  pf.st.first = __builtin_amdgcn_readfirstlane(roff_s[r]);
+  pf.st.n = __builtin_amdgcn_readfirstlane(roff_s[r + 1]) - pf.st.first;
+  const uint2 meta = meta_s[r];
+  pf.st.meta = make_uint2(__builtin_amdgcn_readfirstlane(meta.x), __builtin_amdgcn_readfirstlane(meta.y));
   pf.st.fits = pf.st.n <= (uint32_t)kStageHits;
   if (!pf.st.fits) return;
   if (pf.st.n > 0) {
     const uint32_t last = pf.st.first + pf.st.n - 1;
 #pragma unroll
-    for (int m = 0; m < kPreYz; ++m) pf.yz[m] = d.syz[min(pf.st.first + lane + m * kThreads, last)];
+    for (int m = 0; m < kPreYz; ++m)
+      if ((uint32_t)m * kThreads < pf.st.n) pf.yz[m] = d.syz[min(pf.st.first + lane + m * kThreads, last)];
   }
   const uint32_t nb1 = (pf.st.meta.y & 0xFFFFu) * (pf.st.meta.y >> 16) + 1;   // >= 2: every row has a grid
   const uint32_t blast = pf.st.meta.x + nb1 - 1;
 #pragma unroll
-  for (int m = 0; m < kPreBs; ++m) pf.bs[m] = d.bin_start[min(pf.st.meta.x + lane + m * kThreads, blast)];
+  for (int m = 0; m < kPreBs; ++m)
+    if ((uint32_t)m * kThreads < nb1) pf.bs[m] = d.bin_start[min(pf.st.meta.x + lane + m * kThreads, blast)];
 }
 
 // Write prefetched registers to the LDS stage (call between two barriers).
@@ -568,12 +573,13 @@ __device__ __forceinline__ void commit_row(const Prefetch& pf, float2* yz_s, uin
   const uint32_t lane = threadIdx.x;
   st = pf.st;
   if (!st.fits) return;
-  if (st.n > 0) {
 #pragma unroll
-    for (int m = 0; m < kPreYz; ++m) yz_s[lane + m * kThreads] = pf.yz[m];
-  }
+  for (int m = 0; m < kPreYz; ++m)
+    if ((uint32_t)m * kThreads < st.n) yz_s[lane + m * kThreads] = pf.yz[m];
+  const uint32_t nb1 = (st.meta.y & 0xFFFFu) * (st.meta.y >> 16) + 1;
 #pragma unroll
-  for (int m = 0; m < kPreBs; ++m) bs_s[lane + m * kThreads] = pf.bs[m];
+  for (int m = 0; m < kPreBs; ++m)
+    if ((uint32_t)m * kThreads < nb1) bs_s[lane + m * kThreads] = pf.bs[m];
 }
 
 __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k) {

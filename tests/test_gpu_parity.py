@@ -231,3 +231,46 @@ def test_tracklet_schedules_agree(torch_cuda, workload):
     la, lb = parity.labels_gpu(a["tracks"], n), parity.labels_gpu(b["tracks"], n)
     either = (la >= 0) | (lb >= 0)
     assert np.mean(la[either] == lb[either]) >= parity.MIN_AGREEMENT
+
+
+def _with_dense_rows(ev, rows, n_extra, seed=11):
+    """Copy of a one-sector event with n_extra uniform noise hits added to each listed row."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    row_x, row_half_y = synth.row_geometry()
+    ys, zs, parts, yt, zt, counts = [], [], [], [], [], []
+    for r in range(R):
+        a, b = int(ev.row_offsets[r]), int(ev.row_offsets[r + 1])
+        y, z = [ev.y[a:b]], [ev.z[a:b]]
+        p, ty, tz = [ev.particle[a:b]], [ev.y_true[a:b]], [ev.z_true[a:b]]
+        if r in rows:
+            Y = float(row_half_y[r])
+            y.append(rng.uniform(-Y, Y, n_extra).astype(np.float32))
+            z.append(rng.uniform(float(ev.sector_z_lo[0]), float(ev.sector_z_hi[0]), n_extra).astype(np.float32))
+            p.append(np.full(n_extra, -1, np.int32))
+            ty.append(np.full(n_extra, np.nan))
+            tz.append(np.full(n_extra, np.nan))
+        for lst, dst in ((y, ys), (z, zs), (p, parts), (ty, yt), (tz, zt)):
+            dst.append(np.concatenate(lst))
+        counts.append(len(ys[-1]))
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.uint32)
+    n = int(offs[-1])
+    return dataclasses.replace(ev, row_offsets=offs, y=np.concatenate(ys), z=np.concatenate(zs),
+                               charge=np.zeros(n, np.uint16), particle=np.concatenate(parts),
+                               y_true=np.concatenate(yt), z_true=np.concatenate(zt), name=ev.name + "+dense rows")
+
+
+def test_huge_rows_take_the_global_memory_paths(torch_cuda):
+    """Rows of 13k hits: K1 sorts them in global memory (> 4096 hits), K2 tiles
+    whose reachable z-line runs exceed the LDS stage search global memory, the
+    selector falls back to its global-memory kernels (a single row exceeds the
+    LDS tile) and K5 runs one lane per tracklet.  Same bars as everywhere."""
+    ev = _with_dense_rows(synth.single_sector(seed=1), rows=(40, 41, 42), n_extra=13000)
+    print("case: single_sector seed=1 + 3 rows x 13000 noise hits, N=", ev.n_clusters, flush=True)
+    assert int(np.diff(ev.row_offsets.astype(np.int64)).max()) > 12288
+    tr = _tracker(ev)
+    g = parity.gpu_run(tr, ev)
+    o = _oracle(ev)
+    parity.compare_c1_c4(g, o, R)
+    _check_tracklets(parity.tracklet_stats(g, o, R), "dense rows")
+    _check_tracks(parity.compare_tracks(g["tracks"], o, ev.n_clusters), "dense rows")
