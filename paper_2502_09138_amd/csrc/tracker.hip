@@ -38,7 +38,8 @@ tpc_status fail(tpc_status st, const std::string& msg) {
 
 constexpr double kCB = 0.00299792458;
 constexpr uint64_t kAlign = 256;
-constexpr uint32_t kSelectTileWords = 12288;   // 48 KB of LDS per selector tile
+constexpr uint32_t kSelectTileWords = 12288;     // 48 KB of LDS per selector tile at most
+constexpr uint32_t kSelectTilePreferred = 4096;  // 16 KB: multi-row tiles above this keep too few tiles resident
 
 struct Layout {   // byte offsets of every workspace buffer
   uint64_t row_off, rows, secs, row_dims, row_meta, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
@@ -482,18 +483,21 @@ tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t*
     d.n_link_tiles = nt;
     HIP_TRY(hipMemcpyAsync((void*)d.tile_off, t->h_tile_off, (SR + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st));
   }
-  // selector tile: the most rows per tile (8, 4, 2, 1) whose largest sector row
-  // block fits the LDS budget; 0 = rows too large, global-memory selector.
-  // Per-tile owned counts are bytes, so tiles need at most 255 rows per sector.
+  // selector tile: 4 rows, or 2 when a 4-row block would need more than
+  // kSelectTilePreferred words of LDS (fewer resident tiles), or 1 row up to
+  // kSelectTileWords; 0 = rows too large, global-memory selector.  (Measured:
+  // central event 4 rows 0.126 ms vs 8 rows 0.163 ms; 32-orbit frame 2 rows
+  // 1.02 ms vs 4 rows 1.25 ms.)  Per-tile owned counts are bytes, so tiles
+  // need at most 255 rows per sector.
   uint32_t tile_rows = 0, tile_cap = 0;
-  for (uint32_t tr = 8; tr >= 1 && tile_rows == 0 && R <= 255; tr /= 2) {
+  for (uint32_t tr = 4; tr >= 1 && tile_rows == 0 && R <= 255; tr /= 2) {
     uint32_t mx = 0;
     for (uint32_t s = 0; s < S; ++s)
       for (uint32_t ra = 0; ra < R; ra += tr) {
         const uint32_t rb = std::min(R, ra + tr);
         mx = std::max(mx, f->row_offsets[s * R + rb] - f->row_offsets[s * R + ra]);
       }
-    if (mx <= kSelectTileWords) {
+    if (mx <= (tr == 1 ? kSelectTileWords : kSelectTilePreferred)) {
       tile_rows = tr;
       tile_cap = std::max(mx, 1u);
     }
