@@ -101,6 +101,58 @@ def cpu_baseline(ev, budget_s):
                        f"{done_clusters} clusters), full C1-C7, one thread, {t_total:.1f} s", seconds=t_total)
 
 
+def copy_bandwidth(torch, dev, mib=1024, reps=5):
+    """Device-to-device copy of a 1 GiB buffer: the HBM bandwidth a plain streaming kernel achieves."""
+    a = torch.empty(mib << 20, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    return {"value": round(2.0 * (mib << 20) / (ms * 1e-3) / 1e9, 1), "unit": "GB/s",
+            "note": f"read + write of a {mib} MiB device copy, mean of {reps}"}
+
+
+def _oracle_sector(args):
+    cfg, ro, y, z, lo, hi = args
+    from oracle import oracle
+    t0 = time.perf_counter()
+    oracle.Run(cfg, ro, y, z, lo, hi).run_all()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_pool(ev, budget_s):
+    """The same oracle, one sector per task on a process pool of all host cores (cores counted as the pool size)."""
+    import multiprocessing as mp
+    from paper_2502_09138_amd.config import default_config
+    cfg = default_config().as_dict()
+    cores = max(1, min(16, os.cpu_count() or 1))
+    tasks = []
+    for s in range(ev.n_sectors):
+        sub = ev.sector_slice([s])
+        tasks.append((cfg, sub.row_offsets, sub.y, sub.z, sub.sector_z_lo, sub.sector_z_hi))
+    sizes = [int(t[1][-1]) for t in tasks]
+    done, t_wall, passes = 0, 0.0, 0
+    with mp.get_context("spawn").Pool(cores) as pool:
+        pool.map(_oracle_sector, tasks[:cores])          # start-up outside the timing
+        while t_wall < budget_s:
+            t0 = time.perf_counter()
+            pool.map(_oracle_sector, tasks, chunksize=1)
+            t_wall += time.perf_counter() - t0
+            done += sum(sizes)
+            passes += 1
+    return {"value": done / t_wall, "unit": "clusters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{passes} passes over the workload's {ev.n_sectors} sectors ({done} clusters), one sector per "
+                      f"task on {cores} processes, {t_wall:.1f} s wall"}
+
+
 def tr_schedule_rowsync(schedule, ev):
     """Which K5 kernel runs: the row-synchronous one when forced, or in auto mode when every row fits its stage."""
     if schedule in (1, 2):
@@ -291,10 +343,13 @@ def main():
         "roofline_passes": roof,
     }
     tr.close()
+    rec["achievable_copy"] = copy_bandwidth(torch, dev)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         cb = cpu_baseline(ev, args.cpu_budget)
         rec["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        log("bench: timing the oracle on all host cores")
+        rec["cpu_baseline_all_cores"] = cpu_baseline_pool(ev, args.cpu_budget)
     else:
         rec["cpu_baseline"] = None
     print(json.dumps(rec), flush=True)
