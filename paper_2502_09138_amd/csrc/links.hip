@@ -30,36 +30,64 @@ struct RowView {
   float y_lo, inv_wy, z_lo, inv_wz;
 };
 
-// Positions [lo, hi) of candidate bins for a window around (y, z), one z-line at a time.
+// Candidates of the bins covering a window around (y, z): fn(q, (y, z)) for
+// every hit q (relative to v.off) of those bins.  A lane walks its z-lines as
+// one flat sequence of groups of kGroup hits whose reads are issued together
+// (indices clamped to the z-line), so a wave runs for the largest per-lane
+// candidate count rather than the sum of per-line maxima.  The order in which
+// candidates are visited does not matter: every decision below breaks ties
+// explicitly.
+constexpr int kGroup = 4;
+
 template <class Fn>
 __device__ __forceinline__ void for_window(const RowView& v, float y, float z, float wy, float wz, Fn fn) {
 #pragma clang fp contract(off)
   const float py = wy + kWinPad, pz = wz + kWinPad;
   const int iy0 = bin1(y - py, v.y_lo, v.inv_wy, v.ny), iy1 = bin1(y + py, v.y_lo, v.inv_wy, v.ny);
   const int iz0 = bin1(z - pz, v.z_lo, v.inv_wz, v.nz), iz1 = bin1(z + pz, v.z_lo, v.inv_wz, v.nz);
-  for (int iz = iz0; iz <= iz1; ++iz) {
-    const uint32_t lo = v.bs[iz * v.ny + iy0 - v.bofs] - v.off, hi = v.bs[iz * v.ny + iy1 + 1 - v.bofs] - v.off;
-    for (uint32_t q = lo; q < hi; ++q) fn(q);
+  int iz = iz0;
+  uint32_t q = v.bs[iz * v.ny + iy0 - v.bofs] - v.off, hi = v.bs[iz * v.ny + iy1 + 1 - v.bofs] - v.off;
+  for (;;) {
+    while (q >= hi && iz < iz1) {
+      ++iz;
+      q = v.bs[iz * v.ny + iy0 - v.bofs] - v.off;
+      hi = v.bs[iz * v.ny + iy1 + 1 - v.bofs] - v.off;
+    }
+    if (q >= hi) break;
+    float2 c[kGroup];
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) c[j] = v.yz[min(q + j, hi - 1)];
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j)
+      if (q + j < hi) fn(q + j, c[j]);
+    q += kGroup;
   }
 }
 
 // Candidate slots per lane for the passing hits of row r+1 (mean 1.6, max 7
-// on a central event); a hit with more falls back to rescanning the window.
+// on a central event), held in registers; a hit with more falls back to
+// rescanning the window.
 constexpr int kUpSlots = 8;
 
 // Links of one hit (sorted position p, coordinates h) of row rc between rows dn and up.
 __device__ __forceinline__ void link_hit(const DevPtrs& d, uint32_t p, float2 h, const RowView& dn, const RowView& up,
-                                         const RowConst& rc, float rho, uint16_t* slots) {
+                                         const RowConst& rc, float rho) {
 #pragma clang fp contract(off)
   const float t = rc.t;
   int32_t bu = -1, bd = -1;
   float best = 0.0f;
-  // passing candidates of row r+1, collected once
+  // passing candidates of row r+1, collected once (registers: unrolled, predicated slot writes)
   int nu = 0;
-  for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu) {
-    const float2 pu = up.yz[qu];
+  uint32_t sq[kUpSlots];
+  float2 sc[kUpSlots];
+  for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu, float2 pu) {
     if (!(fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up)) return;
-    if (nu < kUpSlots) slots[nu] = (uint16_t)qu;
+#pragma unroll
+    for (int j = 0; j < kUpSlots; ++j)
+      if (j == nu) {
+        sq[j] = qu;
+        sc[j] = pu;
+      }
     ++nu;
   });
   if (nu == 0) {
@@ -67,8 +95,7 @@ __device__ __forceinline__ void link_hit(const DevPtrs& d, uint32_t p, float2 h,
     d.down0[p] = -1;
     return;
   }
-  auto pair = [&](const float2 pd, int32_t gd, uint32_t qu) {
-    const float2 pu = up.yz[qu];
+  auto pair = [&](const float2 pd, int32_t gd, uint32_t qu, const float2 pu) {
     const float yp = pd.x + t * (pu.x - pd.x);
     const float zp = pd.y + t * (pu.y - pd.y);
     const float ey = h.x - yp, ez = h.y - zp;
@@ -81,16 +108,16 @@ __device__ __forceinline__ void link_hit(const DevPtrs& d, uint32_t p, float2 h,
       bd = gd;
     }
   };
-  for_window(dn, h.x, h.y, rc.wy_dn, rc.wz_dn, [&](uint32_t qd) {
-    const float2 pd = dn.yz[qd];
+  for_window(dn, h.x, h.y, rc.wy_dn, rc.wz_dn, [&](uint32_t qd, float2 pd) {
     if (!(fabsf(pd.x - h.x) <= rc.wy_dn && fabsf(pd.y - h.y) <= rc.wz_dn)) return;
     const int32_t gd = (int32_t)(dn.off + qd);
     if (nu <= kUpSlots) {
-      for (int k = 0; k < nu; ++k) pair(pd, gd, slots[k]);
+#pragma unroll
+      for (int k = 0; k < kUpSlots; ++k)
+        if (k < nu) pair(pd, gd, sq[k], sc[k]);
     } else {
-      for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu) {
-        const float2 pu = up.yz[qu];
-        if (fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up) pair(pd, gd, qu);
+      for_window(up, h.x, h.y, rc.wy_up, rc.wz_up, [&](uint32_t qu, float2 pu) {
+        if (fabsf(pu.x - h.x) <= rc.wy_up && fabsf(pu.y - h.y) <= rc.wz_up) pair(pd, gd, qu, pu);
       });
     }
   });
@@ -149,7 +176,6 @@ __device__ __forceinline__ RowView adjacent_view(const DevPtrs& d, uint32_t sr, 
 __global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho) {
   __shared__ float2 lyz[2][kSliceHits];
   __shared__ uint32_t lbs[2][kSliceBins];
-  __shared__ uint16_t slots[kThreads][kUpSlots];
   const uint32_t tile = blockIdx.x;
   const uint32_t sr = d.tile_sr[tile], R = d.R, row = sr % R;
   const uint32_t a = d.row_off[sr] + (tile - d.tile_off[sr]) * kThreads;
@@ -173,7 +199,7 @@ __global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho) {
   const RowView dn = adjacent_view(d, sr - 1, zmin, zmax, rc.wz_dn, stage, lyz[0], lbs[0]);
   const RowView up = adjacent_view(d, sr + 1, zmin, zmax, rc.wz_up, stage, lyz[1], lbs[1]);
   __syncthreads();
-  if (mine) link_hit(d, p, h, dn, up, rc, rho, slots[lane]);
+  if (mine) link_hit(d, p, h, dn, up, rc, rho);
 }
 
 }  // namespace
