@@ -179,9 +179,8 @@ __device__ __forceinline__ void set_c0(Trk& t, const KfConst& k) {
 // (see search_lds); the kGroup loads of a group are issued together.
 constexpr int kGroup = 4;
 
-__device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const RowK& rk, const SectorConst& sc,
-                                          const Trk& t, const KfConst& k, float zref) {
-  const uint2 meta = d.row_meta[sr];
+__device__ __forceinline__ int32_t search_m(const DevPtrs& d, uint2 meta, const RowK& rk, const SectorConst& sc,
+                                            const Trk& t, const KfConst& k, float zref) {
   const float sy2 = t.c[0] + k.vy, sz2 = t.c[2] + k.vz;
   const float wy = fminf(k.gate * fsqrt(sy2), k.cap), wz = fminf(k.gate * fsqrt(sz2), k.cap);
   const float isy = frcp(sy2), isz = frcp(sz2);
@@ -221,6 +220,11 @@ __device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const R
     q += kGroup;
   }
   return best;
+}
+
+__device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const RowK& rk, const SectorConst& sc,
+                                          const Trk& t, const KfConst& k, float zref) {
+  return search_m(d, d.row_meta[sr], rk, sc, t, k, zref);
 }
 
 // The same search over a row staged in LDS: (y, z) of the row's hits at
@@ -414,15 +418,17 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
     float chi2 = 0.0f;
     bool ok = true;
     float xprev = lrows[r0].x;
-    // chain fit (no gate)
+    // chain fit (no gate); the next chain hit is loaded while this row is fitted
+    float2 hnx = r0 + 1 <= rl ? d.syz[H[(size_t)(r0 + 1) * T]] : make_float2(0.0f, 0.0f);
     for (uint32_t r = r0 + 1; r <= rl; ++r) {
+      const float2 h = hnx;
+      if (r + 1 <= rl) hnx = d.syz[H[(size_t)(r + 1) * T]];
       const float x = lrows[r].x;
       if (!propagate(t, x - xprev, k)) {
         ok = false;
         break;
       }
       xprev = x;
-      const float2 h = d.syz[H[(size_t)r * T]];
       update(t, h.x, h.y - zref, k, chi2);
     }
     if (!ok) {
@@ -436,13 +442,16 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
     for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
     uint32_t rout = rl;
     int miss = 0;
+    uint2 mnx = rl + 1 < R ? d.row_meta[srb + rl + 1] : make_uint2(0u, 0u);   // next row's grid word, one row ahead
     for (uint32_t r = rl + 1; r < R; ++r) {
+      const uint2 meta = mnx;
+      if (r + 1 < R) mnx = d.row_meta[srb + r + 1];
       const RowK rk = lrows[r];
       ++steps;
       if (!propagate(t, rk.x - xprev, k)) break;
       xprev = rk.x;
       if (fabsf(t.p[0]) > rk.half_y + k.margin) break;
-      const int32_t h = search(d, srb + r, rk, sc, t, k, zref);
+      const int32_t h = search_m(d, meta, rk, sc, t, k, zref);
       H[(size_t)r * T] = h;
       if (h >= 0) {
         const float2 hm = d.syz[h];
@@ -470,18 +479,34 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
     uint32_t rin = rout;
     xprev = lrows[rout].x;
     miss = 0;
+    // the outward pass's hit of the next row and its coordinates are loaded one
+    // and two rows ahead, the next row's grid word one row ahead
+    auto known = [&](int r) { return r >= (int)r0 && r >= 0 ? H[(size_t)r * T] : -1; };
+    int32_t hA = known((int)rout - 1), hB = known((int)rout - 2);
+    float2 vA = hA >= 0 ? d.syz[hA] : make_float2(0.0f, 0.0f);
+    uint2 mA = rout >= 1 ? d.row_meta[srb + rout - 1] : make_uint2(0u, 0u);
     for (int r = (int)rout - 1; r >= 0; --r) {
+      const int32_t hk = hA;
+      const float2 vk = vA;
+      const uint2 meta = mA;
+      hA = hB;
+      vA = hB >= 0 ? d.syz[hB] : make_float2(0.0f, 0.0f);
+      hB = known(r - 2);
+      if (r >= 1) mA = d.row_meta[srb + (uint32_t)r - 1];
       const RowK rk = lrows[r];
       ++steps;
       if (!propagate(t, rk.x - xprev, k)) break;
       xprev = rk.x;
       const bool below = (uint32_t)r < r0;
       if (below && fabsf(t.p[0]) > rk.half_y + k.margin) break;
-      int32_t h = below ? -1 : H[(size_t)r * T];
-      if (h < 0) h = search(d, srb + (uint32_t)r, rk, sc, t, k, zref);
+      int32_t h = hk;
+      float2 hm = vk;
+      if (h < 0) {
+        h = search_m(d, meta, rk, sc, t, k, zref);
+        if (h >= 0) hm = d.syz[h];
+      }
       H[(size_t)r * T] = h;
       if (h >= 0) {
-        const float2 hm = d.syz[h];
         update(t, hm.x, hm.y - zref, k, chi2);
         ++nh;
         snap = t;
