@@ -75,6 +75,8 @@ def make_workload(name):
         return synth.time_frame(seed=3), dict(workload="time_frame", seed=3, n_orbits=32, rate_khz=50)
     if name == "uneven_chunks":
         return synth.uneven_chunks(), dict(workload="uneven_chunks", seed0=1000, n_chunks=512)
+    if name == "pp_frame":
+        return synth.pp_time_frame(seed=50, n_orbits=2), dict(workload="pp_frame", seed=50, n_orbits=2, rate_khz=650)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -213,7 +215,7 @@ def main():
                     help="instead of the plain bench: serve a Poisson trace of this many seconds with one slot (plain "
                          "path) and with --slots slots, report p50/p99 latency and clusters/s of both")
     ap.add_argument("--slots", type=int, default=3)
-    ap.add_argument("--rate", type=float, default=200.0, help="trace arrival rate (requests/s) for --serve")
+    ap.add_argument("--rate", type=float, default=800.0, help="trace arrival rate (requests/s) for --serve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sectors and time frames "
