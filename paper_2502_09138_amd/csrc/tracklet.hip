@@ -175,12 +175,13 @@ __device__ __forceinline__ void set_c0(Trk& t, const KfConst& k) {
 }
 
 // Grid search in row sr for the candidate closest to the prediction; -1 if
-// none.  z-lines are walked as one flat sequence of candidate groups per lane
-// (see search_lds); the kGroup loads of a group are issued together.
+// none, else its position, with its (y, z) in hv.  z-lines are walked as one
+// flat sequence of candidate groups per lane (see search_lds); the kGroup loads
+// of a group are issued together.
 constexpr int kGroup = 4;
 
 __device__ __forceinline__ int32_t search_m(const DevPtrs& d, uint2 meta, const RowK& rk, const SectorConst& sc,
-                                            const Trk& t, const KfConst& k, float zref) {
+                                            const Trk& t, const KfConst& k, float zref, float2& hv) {
   const float sy2 = t.c[0] + k.vy, sz2 = t.c[2] + k.vz;
   const float wy = fminf(k.gate * fsqrt(sy2), k.cap), wz = fminf(k.gate * fsqrt(sz2), k.cap);
   const float isy = frcp(sy2), isz = frcp(sz2);
@@ -214,6 +215,7 @@ __device__ __forceinline__ int32_t search_m(const DevPtrs& d, uint2 meta, const 
         if (best < 0 || dd < bd) {
           best = (int32_t)(q + j);
           bd = dd;
+          hv = h[j];
         }
       }
     }
@@ -223,8 +225,8 @@ __device__ __forceinline__ int32_t search_m(const DevPtrs& d, uint2 meta, const 
 }
 
 __device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const RowK& rk, const SectorConst& sc,
-                                          const Trk& t, const KfConst& k, float zref) {
-  return search_m(d, d.row_meta[sr], rk, sc, t, k, zref);
+                                          const Trk& t, const KfConst& k, float zref, float2& hv) {
+  return search_m(d, d.row_meta[sr], rk, sc, t, k, zref, hv);
 }
 
 // The same search over a row staged in LDS: (y, z) of the row's hits at
@@ -451,10 +453,10 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
       if (!propagate(t, rk.x - xprev, k)) break;
       xprev = rk.x;
       if (fabsf(t.p[0]) > rk.half_y + k.margin) break;
-      const int32_t h = search_m(d, meta, rk, sc, t, k, zref);
+      float2 hm = make_float2(0.0f, 0.0f);
+      const int32_t h = search_m(d, meta, rk, sc, t, k, zref, hm);
       H[(size_t)r * T] = h;
       if (h >= 0) {
-        const float2 hm = d.syz[h];
         update(t, hm.x, hm.y - zref, k, chi2);
 #pragma unroll
         for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
@@ -502,8 +504,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
       int32_t h = hk;
       float2 hm = vk;
       if (h < 0) {
-        h = search_m(d, meta, rk, sc, t, k, zref);
-        if (h >= 0) hm = d.syz[h];
+        h = search_m(d, meta, rk, sc, t, k, zref, hm);
       }
       H[(size_t)r * T] = h;
       if (h >= 0) {
@@ -705,8 +706,9 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
           } else {
             int32_t h = hchain;
             if (!chain) {
+              float2 unused;
               h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
-                          : search(d, srb + r, rk, sc, t, k, zref);
+                          : search(d, srb + r, rk, sc, t, k, zref, unused);
               H[(size_t)r * T] = h;
             }
             if (h >= 0) {
@@ -773,9 +775,10 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
             down = false;
           } else {
             int32_t h = below ? -1 : hrow;
+            float2 unused;
             if (h < 0)
               h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
-                          : search(d, srb + (uint32_t)rr, rk, sc, t, k, zref);
+                          : search(d, srb + (uint32_t)rr, rk, sc, t, k, zref, unused);
             H[(size_t)rr * T] = h;
             if (h >= 0) {
               const float2 hm = st.fits ? yz_s[(uint32_t)h - st.first] : d.syz[h];
