@@ -17,10 +17,12 @@
 //   k_accept       sums the tiles, applies the acceptance rule, turns own_part
 //                  into per-tile prefixes and packs (owned << 32) | accepted for
 //                  one 64-bit scan giving track index and cluster offset;
-//   k_emit_tiles   writes the owned cluster ids of each accepted tracklet at
-//                  offset + prefix, row by row (ascending row order);
 //   k_records      writes the per-track records (canonical order = tracklet
-//                  order = ascending start position);
+//                  order = ascending start position) and the track -> tracklet
+//                  list;
+//   k_emit_tiles   walks the sector's tracks (not all its tracklets) and writes
+//                  the owned cluster ids of each at offset + prefix, row by row
+//                  (ascending row order);
 //   k_finish       totals and capacity flags.
 // Rows too large for an LDS tile use the same steps with W in global memory,
 // one thread per tracklet (k_claim_g / k_own_g / k_emit_g).
@@ -125,14 +127,15 @@ __global__ void __launch_bounds__(kThreads) k_emit_tiles(DevPtrs d, KfConst k, u
   const Tile tl = tile_of(d, tile_rows, n_tiles);
   const uint32_t T = d.tcap, tt = blockIdx.x % n_tiles;
   for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) wt[j] = d.W[tl.first + j];
+  // the sector's tracks: [track index of its first tracklet, ... of the next sector's), in track order
+  const uint32_t v0 = (uint32_t)(d.tk_scan[tl.ts] & 0xFFFFFFFFull);
+  const uint32_t v1 = min((uint32_t)(d.tk_scan[tl.te] & 0xFFFFFFFFull), d.max_tracks);
   __syncthreads();
-  for (uint32_t i = tl.ts + threadIdx.x; i < tl.te; i += blockDim.x) {
+  for (uint32_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+    const uint32_t i = d.acc_list[v];
     const unsigned long long pk = d.tk_pack[i];
-    if (!(pk & 1ull)) continue;
-    const unsigned long long pre = d.tk_scan[i];
-    const uint32_t ti = (uint32_t)(pre & 0xFFFFFFFFull);
-    const unsigned long long co = pre >> 32;
-    if (ti >= d.max_tracks || co + (pk >> 32) > d.max_track_clusters) continue;   // flagged in k_finish
+    const unsigned long long co = d.tk_scan[i] >> 32;
+    if (co + (pk >> 32) > d.max_track_clusters) continue;   // flagged in k_finish
     const int32_t nh = d.tk_info[i];
     const int32_t a = max((int32_t)tl.ra, d.tk_info[T + i]), b = min((int32_t)tl.rb - 1, d.tk_info[2 * T + i]);
     if (a > b) continue;
@@ -156,7 +159,9 @@ __global__ void __launch_bounds__(kThreads) k_records(DevPtrs d, KfConst k) {
     const unsigned long long pre = d.tk_scan[i];
     const uint32_t ti = (uint32_t)(pre & 0xFFFFFFFFull);
     const unsigned long long co = pre >> 32;
-    if (ti >= d.max_tracks || co + (pk >> 32) > d.max_track_clusters) continue;
+    if (ti >= d.max_tracks) continue;                          // flagged in k_finish
+    d.acc_list[ti] = i;                                        // track -> tracklet, for the tiled emit
+    if (co + (pk >> 32) > d.max_track_clusters) continue;
     const int32_t nh = d.tk_info[i];
     d.out_sector[ti] = d.start_sr[i] / d.R;
     d.out_start[ti] = d.start_pos[i];
@@ -270,6 +275,7 @@ void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipSt
     hipLaunchKernelGGL(k_own_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
     hipLaunchKernelGGL(k_accept, dim3(blocks), dim3(kThreads), 0, s, d, k, tile_rows);
     launch_scan_u64(d.tk_pack, d.tk_scan, &d.hdr->n_starts, d.tcap, d.scan_blocks, s);
+    hipLaunchKernelGGL(k_records, dim3(blocks), dim3(kThreads), 0, s, d, k);
     hipLaunchKernelGGL(k_emit_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
   } else {
     hipLaunchKernelGGL(k_clear_w, dim3(xcd_grid(std::min<uint32_t>(8192, std::max<uint32_t>(1, (d.N + kThreads - 1) / kThreads)))),
@@ -278,8 +284,8 @@ void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipSt
     hipLaunchKernelGGL(k_own_g, dim3(blocks), dim3(kThreads), 0, s, d, k);
     launch_scan_u64(d.tk_pack, d.tk_scan, &d.hdr->n_starts, d.tcap, d.scan_blocks, s);
     hipLaunchKernelGGL(k_emit_g, dim3(blocks), dim3(kThreads), 0, s, d, k);
+    hipLaunchKernelGGL(k_records, dim3(blocks), dim3(kThreads), 0, s, d, k);
   }
-  hipLaunchKernelGGL(k_records, dim3(blocks), dim3(kThreads), 0, s, d, k);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, d);
 }
 

@@ -89,6 +89,7 @@ struct DevPtrs {
   uint8_t* own_part;         // [R * Tcap] owned hits of a tracklet per selector tile (then prefixes)
   unsigned long long* tk_pack;   // [Tcap] (owned << 32) | accepted
   unsigned long long* tk_scan;   // [Tcap + 1] exclusive scan of tk_pack
+  uint32_t* acc_list;        // [max_tracks] tracklet of each track (track order)
   // outputs
   uint32_t* out_sector;
   uint32_t* out_start;

@@ -44,7 +44,7 @@ constexpr uint32_t kSelectTilePreferred = 4096;  // 16 KB: multi-row tiles above
 struct Layout {   // byte offsets of every workspace buffer
   uint64_t row_off, rows, secs, row_dims, row_meta, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
       row_start_off, start_pos, start_sr, wave_off, tile_off, tile_sr, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, W, own_part, tk_pack,
-      tk_scan,
+      tk_scan, acc_list,
       out_sector, out_start, out_first, out_clusters, out_xref, out_param, out_cov, out_chi2, out_ndf, scan_blocks,
       hdr, in_y, in_z, total;
 };
@@ -103,6 +103,7 @@ Layout layout_of(const Caps& k) {
   L.own_part = take((uint64_t)k.R * k.T);
   L.tk_pack = take(k.T * 8);
   L.tk_scan = take((k.T + 1) * 8);
+  L.acc_list = take((k.MT + 1) * 4);
   L.out_sector = take(k.MT * 4);
   L.out_start = take(k.MT * 4);
   L.out_first = take((k.MT + 1) * 4);
@@ -335,6 +336,7 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   d.own_part = (uint8_t*)(w + lay.own_part);
   d.tk_pack = (unsigned long long*)(w + lay.tk_pack);
   d.tk_scan = (unsigned long long*)(w + lay.tk_scan);
+  d.acc_list = (uint32_t*)(w + lay.acc_list);
   d.out_sector = (uint32_t*)(w + lay.out_sector);
   d.out_start = (uint32_t*)(w + lay.out_start);
   d.out_first = (uint32_t*)(w + lay.out_first);
