@@ -230,9 +230,10 @@ class Tracker:
         else:
             assert y.is_cuda and z.is_cuda and y.dtype == self._torch.float32 and z.dtype == self._torch.float32
             assert y.is_contiguous() and z.is_contiguous()
+            # ordered after the work that produced y and z; the tensors stay referenced
+            # (self._inputs) until release(), which waits for the request, so the
+            # caching allocator cannot hand their memory out while the kernels read it
             self.stream.wait_stream(self._torch.cuda.current_stream(self.device))
-            y.record_stream(self.stream)
-            z.record_stream(self.stream)
             f.y, f.z = y.data_ptr(), z.data_ptr()
             f.flags = TPC_IN_DEVICE
         self._inputs = (y, z, row_offsets, z_lo, z_hi)   # borrowed until the request completes
