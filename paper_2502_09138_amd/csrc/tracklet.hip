@@ -232,10 +232,15 @@ __device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const R
 // The same search over a row staged in LDS: (y, z) of the row's hits at
 // yz[q - first] and its bin starts (global positions) in bs[].  It is run by the
 // two lanes of a pair that carry the same tracklet: on every z-line they take
-// alternate groups of kGroup candidates (indices clamped to the z-line, so every
-// read stays in the staged row), walking the z-lines as one flat sequence, and
-// then exchange their best candidates.  The result -- smallest deviation, ties
-// to the smaller position -- is the same as a single ascending scan.
+// alternate groups of kGroup candidates, walking the z-lines as one flat
+// sequence, and then exchange their best candidates (a DPP swap inside the
+// pair, no LDS round trip).  A group is read whole: its entries past the
+// z-line's end (at most kGroup - 1, inside the stage's slack) are masked out.
+// The result -- smallest deviation, ties to the smaller position -- is the same
+// as a single ascending scan.
+__device__ __forceinline__ int pair_swap(int v) {   // value of the other lane of the pair (quad_perm 1,0,3,2)
+  return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);
+}
 __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* bs, uint32_t first, uint2 meta,
                                               const RowK& rk, const SectorConst& sc, const Trk& t, const KfConst& k,
                                               float zref, uint32_t half) {
@@ -261,9 +266,10 @@ __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* 
       hi = bs[iz * ny + iy1 + 1];
     }
     if (q >= hi) break;
+    const float2* g = yz + (q - first);
     float2 h[kGroup];
 #pragma unroll
-    for (int j = 0; j < kGroup; ++j) h[j] = yz[min(q + j, hi - 1) - first];
+    for (int j = 0; j < kGroup; ++j) h[j] = g[j];
 #pragma unroll
     for (int j = 0; j < kGroup; ++j) {
       const float dy = h[j].x - yp, dz = (h[j].y - zref) - zp;
@@ -278,8 +284,8 @@ __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* 
     q += kPair * kGroup;
   }
   // the pair's two candidates: smaller deviation, ties to the smaller position
-  const int32_t ob = __shfl_xor(best, 1, kWave);
-  const float od = __shfl_xor(bd, 1, kWave);
+  const int32_t ob = pair_swap(best);
+  const float od = __int_as_float(pair_swap(__float_as_int(bd)));
   if (ob >= 0 && (best < 0 || od < bd || (od == bd && ob < best))) {
     best = ob;
     bd = od;
@@ -385,10 +391,11 @@ __device__ __forceinline__ void store_tracklet(const DevPtrs& d, uint32_t i, int
 // of a few sectors only, which stay resident in that XCD's L2.
 __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
   __shared__ RowK lrows[kMaxRows];
-  load_rows(d, lrows);
   const uint32_t nt = min(d.hdr->n_starts, d.tcap);
   const uint32_t R = d.R, T = d.tcap;
   const XcdSched sch = xcd_sched(nt);
+  if (sch.first >= sch.end) return;   // the grid is sized for the tracklet capacity
+  load_rows(d, lrows);
   unsigned long long my_steps = 0;
   for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
     const uint32_t i = vb * kThreads + threadIdx.x;
@@ -545,6 +552,7 @@ constexpr int kPreBs = (kStageBins + kThreads - 1) / kThreads;
 struct Stage {
   uint32_t first, n;
   uint2 meta;
+  RowK rk;
   bool fits;
 };
 
@@ -570,15 +578,29 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 // table, so no load here waits on another; only the 64-entry chunks the row
 // needs are loaded (a scalar decision), each lane from an index clamped into
 // the row, so the loads need no per-lane predication.
-__device__ __forceinline__ void prefetch_row(const DevPtrs& d, const uint32_t* roff_s, const uint2* meta_s, uint32_t r,
-                                             Prefetch& pf) {
+// Issue priority of a wave from the rows it still has to step through (a
+// longest-remaining-first order for the waves that share a SIMD).
+__device__ __forceinline__ void set_priority(uint32_t rows_left) {
+  if (rows_left >= 225) __builtin_amdgcn_s_setprio(3);
+  else if (rows_left >= 150) __builtin_amdgcn_s_setprio(2);
+  else if (rows_left >= 75) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float((int)__builtin_amdgcn_readfirstlane((uint32_t)__float_as_int(v)));
+}
+template <bool kAllFit>
+__device__ __forceinline__ void prefetch_row(const DevPtrs& d, const RowK* lrows, const uint32_t* roff_s,
+                                             const uint2* meta_s, uint32_t r, Prefetch& pf) {
   const uint32_t lane = threadIdx.x;
   // wave-uniform row facts, so that the load count below is a scalar decision
   pf.st.first = __builtin_amdgcn_readfirstlane(roff_s[r]);
   pf.st.n = __builtin_amdgcn_readfirstlane(roff_s[r + 1]) - pf.st.first;
   const uint2 meta = meta_s[r];
   pf.st.meta = make_uint2(__builtin_amdgcn_readfirstlane(meta.x), __builtin_amdgcn_readfirstlane(meta.y));
-  pf.st.fits = pf.st.n <= (uint32_t)kStageHits;
+  const RowK rk = lrows[r];   // the row's constants, for the step that uses the stage
+  pf.st.rk = RowK{uniform_f(rk.x), uniform_f(rk.half_y), uniform_f(rk.y_lo), uniform_f(rk.inv_wy)};
+  pf.st.fits = kAllFit || pf.st.n <= (uint32_t)kStageHits;
   if (!pf.st.fits) return;
   if (pf.st.n > 0) {
     const uint32_t last = pf.st.first + pf.st.n - 1;
@@ -608,13 +630,13 @@ __device__ __forceinline__ void commit_row(const Prefetch& pf, float2* yz_s, uin
     if ((uint32_t)m * kThreads < nb1) bs_s[lane + m * kThreads] = pf.bs[m];
 }
 
+template <bool kAllFit>
 __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k) {
   __shared__ RowK lrows[kMaxRows];
-  __shared__ float2 yz_s[kPreYz * kThreads];     // >= kStageHits
+  __shared__ float2 yz_s[kPreYz * kThreads + kGroup];   // >= kStageHits, + slack for whole-group reads
   __shared__ uint32_t bs_s[kPreBs * kThreads];   // >= kStageBins
   __shared__ uint32_t roff_s[kMaxRows + 1];   // the current sector's row offsets
   __shared__ uint2 meta_s[kMaxRows];          // and grid words
-  load_rows(d, lrows);
   const uint32_t R = d.R, T = d.tcap, S = d.S;
   const uint32_t lane = threadIdx.x;
   const uint32_t W = d.wave_off[S];
@@ -622,6 +644,9 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
   const uint32_t per = (W + kXcds - 1) / kXcds;
   const uint32_t xcd = blockIdx.x % kXcds;
   const uint32_t vend = min(W, (xcd + 1) * per);
+  // the grid is sized for the tracklet capacity; blocks without a wave leave at once
+  if (xcd * per + blockIdx.x / kXcds >= vend) return;
+  load_rows(d, lrows);
   unsigned long long my_steps = 0;
   for (uint32_t v = xcd * per + blockIdx.x / kXcds; v < vend; v += gridDim.x / kXcds) {
     // sector of wave v: last s with wave_off[s] <= v
@@ -683,17 +708,24 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
     Prefetch pf;
     uint32_t r = __builtin_amdgcn_readfirstlane(wave_min(up ? r0 + 1 : R));   // wave-uniform from here on
     if (r < R) {
-      prefetch_row(d, roff_s, meta_s, r, pf);
+      prefetch_row<kAllFit>(d, lrows, roff_s, meta_s, r, pf);
       commit_row(pf, yz_s, bs_s, st);
       __syncthreads();
     }
     int32_t hnext = (up && r <= rl && r > r0) ? H[(size_t)r * T] : -1;
+    // Drain every load issued so far (the sector constants, the first row, the
+    // chain hit) before the loop: the compiler's wait counters are tracked per
+    // register across the back edge, and a value still pending from before the
+    // loop would otherwise make every iteration wait for all its loads --
+    // including the prefetch of the next row, which should overlap the step.
+    __builtin_amdgcn_s_waitcnt(0);
     while (r < R && __any(up)) {
-      if (r + 1 < R) prefetch_row(d, roff_s, meta_s, r + 1, pf);
+      set_priority(2 * R - r);   // the rest of this sweep, then (about) the whole inward sweep
+      if (r + 1 < R) prefetch_row<kAllFit>(d, lrows, roff_s, meta_s, r + 1, pf);
       const int32_t hchain = hnext;
       hnext = (up && r + 1 <= rl && r + 1 > r0) ? H[(size_t)(r + 1) * T] : -1;
       if (up && r > r0) {
-        const RowK rk = lrows[r];
+        const RowK rk = st.rk;
         const bool chain = r <= rl;
         if (!chain) ++steps;
         if (!propagate(t, rk.x - xprev, k)) {
@@ -707,12 +739,12 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
             int32_t h = hchain;
             if (!chain) {
               float2 unused;
-              h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
+              h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
                           : search(d, srb + r, rk, sc, t, k, zref, unused);
               H[(size_t)r * T] = h;
             }
             if (h >= 0) {
-              const float2 hm = st.fits ? yz_s[(uint32_t)h - st.first] : d.syz[h];
+              const float2 hm = (kAllFit || st.fits) ? yz_s[(uint32_t)h - st.first] : d.syz[h];
               update(t, hm.x, hm.y - zref, k, chi2);
               if (r >= rl) {
 #pragma unroll
@@ -754,17 +786,19 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
     }
     int32_t rr = (int32_t)__builtin_amdgcn_readfirstlane(wave_max(down ? rout : 0)) - 1;
     if (rr >= 0) {
-      prefetch_row(d, roff_s, meta_s, (uint32_t)rr, pf);
+      prefetch_row<kAllFit>(d, lrows, roff_s, meta_s, (uint32_t)rr, pf);
       commit_row(pf, yz_s, bs_s, st);
       __syncthreads();
     }
     hnext = (down && rr >= (int32_t)r0 && rr < (int32_t)rout) ? H[(size_t)rr * T] : -1;
+    __builtin_amdgcn_s_waitcnt(0);   // as before the outward sweep
     while (rr >= 0 && __any(down)) {
-      if (rr > 0) prefetch_row(d, roff_s, meta_s, (uint32_t)rr - 1, pf);
+      set_priority((uint32_t)rr);
+      if (rr > 0) prefetch_row<kAllFit>(d, lrows, roff_s, meta_s, (uint32_t)rr - 1, pf);
       const int32_t hrow = hnext;
       hnext = (down && rr - 1 >= (int32_t)r0 && rr - 1 < (int32_t)rout) ? H[(size_t)(rr - 1) * T] : -1;
       if (down && rr < (int32_t)rout) {
-        const RowK rk = lrows[rr];
+        const RowK rk = st.rk;
         ++steps;
         if (!propagate(t, rk.x - xprev, k)) {
           down = false;
@@ -777,11 +811,11 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
             int32_t h = below ? -1 : hrow;
             float2 unused;
             if (h < 0)
-              h = st.fits ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
+              h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
                           : search(d, srb + (uint32_t)rr, rk, sc, t, k, zref, unused);
             H[(size_t)rr * T] = h;
             if (h >= 0) {
-              const float2 hm = st.fits ? yz_s[(uint32_t)h - st.first] : d.syz[h];
+              const float2 hm = (kAllFit || st.fits) ? yz_s[(uint32_t)h - st.first] : d.syz[h];
               update(t, hm.x, hm.y - zref, k, chi2);
               ++nh;
               snap = t;
@@ -837,7 +871,10 @@ void launch_tracklets(const DevPtrs& d, const KfConst& k, uint32_t max_row_hits,
     hipLaunchKernelGGL(k_waves, dim3(1), dim3(1024), 0, s, d);
     uint32_t blocks = (d.tcap + kTrkPerWave - 1) / kTrkPerWave + d.S;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_tracklets_rs, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
+    if (max_row_hits <= (uint32_t)kStageHits)   // every row is staged: the kernel carries no global-memory search
+      hipLaunchKernelGGL(k_tracklets_rs<true>, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
+    else
+      hipLaunchKernelGGL(k_tracklets_rs<false>, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
     return;
   }
   uint32_t blocks = (d.tcap + kThreads - 1) / kThreads;
