@@ -79,8 +79,9 @@ Layout layout_of(const Caps& k) {
   L.secs = take((uint64_t)k.Smax * sizeof(SectorConst));
   L.row_dims = take(k.SRmax * 4);
   L.row_meta = take(k.SRmax * 8);
-  L.bin_start = take((k.N + 2 * k.SRmax + 2) * 4);
-  L.syz = take(k.N * 8);
+  // + 4 and + 2 entries: the tracklet stage reads both in 16-byte units
+  L.bin_start = take((k.N + 2 * k.SRmax + 2 + 4) * 4);
+  L.syz = take((k.N + 2) * 8);
   L.sid = take(k.N * 4);
   L.up0 = take(k.N * 4);
   L.down0 = take(k.N * 4);

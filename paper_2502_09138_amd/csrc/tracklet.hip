@@ -544,21 +544,36 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
 // Every search and every measurement read then hits LDS, which takes the
 // dependent global-memory round trips out of the per-row critical path.  Rows
 // larger than the stage fall back to global-memory search for that row.
+//
+// The stage is filled with 16-byte loads that every lane issues
+// unconditionally: the (y, z) pairs from the even index at or below the row's
+// first hit, the bin starts from the multiple of four at or below the row's
+// first bin (both arrays carry padding at their ends, so reads past a row stay
+// inside the allocation).  A load whose slot lies past the row re-reads the
+// first one; the stage entries it fills are never used.
 constexpr int kStageHits = 320;
 constexpr int kStageBins = kStageHits + 2;                       // nBins + 1 <= N_r + 1
-constexpr int kPreYz = (kStageHits + kThreads - 1) / kThreads;   // per-lane prefetch slots
-constexpr int kPreBs = (kStageBins + kThreads - 1) / kThreads;
+constexpr int kPreYz = 3;   // float4 loads per lane: 2 hits each
+constexpr int kPreBs = 2;   // uint4 loads per lane: 4 bin starts each
+// alignment slack (1), whole-group reads past a z-line (kGroup - 1)
+static_assert(kPreYz * kThreads * 2 >= kStageHits + 1 + kGroup - 1, "yz stage too small");
+static_assert(kPreBs * kThreads * 4 >= kStageBins + 3, "bin stage too small");
 
 struct Stage {
-  uint32_t first, n;
+  uint32_t first;   // global index of stage entry 0 (even, <= the row's first hit)
+  uint32_t boff;    // stage index of the row's bin 0
   uint2 meta;
   RowK rk;
   bool fits;
 };
 
+// native vector types: arrays of them stay in registers
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 struct Prefetch {
-  float2 yz[kPreYz];
-  uint32_t bs[kPreBs];
+  f32x4 yz[kPreYz];
+  u32x4 bs[kPreBs];
   Stage st;
 };
 
@@ -579,11 +594,15 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 // needs are loaded (a scalar decision), each lane from an index clamped into
 // the row, so the loads need no per-lane predication.
 // Issue priority of a wave from the rows it still has to step through (a
-// longest-remaining-first order for the waves that share a SIMD).
-__device__ __forceinline__ void set_priority(uint32_t rows_left) {
-  if (rows_left >= 225) __builtin_amdgcn_s_setprio(3);
-  else if (rows_left >= 150) __builtin_amdgcn_s_setprio(2);
-  else if (rows_left >= 75) __builtin_amdgcn_s_setprio(1);
+// longest-remaining-first order for the waves that share a SIMD); `level`
+// holds the wave's current setting, so the instruction is issued on changes only.
+__device__ __forceinline__ void set_priority(uint32_t rows_left, uint32_t& level) {
+  const uint32_t want = (rows_left >= 75) + (rows_left >= 150) + (rows_left >= 225);
+  if (want == level) return;
+  level = want;
+  if (want == 3) __builtin_amdgcn_s_setprio(3);
+  else if (want == 2) __builtin_amdgcn_s_setprio(2);
+  else if (want == 1) __builtin_amdgcn_s_setprio(1);
   else __builtin_amdgcn_s_setprio(0);
 }
 __device__ __forceinline__ float uniform_f(float v) {
@@ -593,48 +612,51 @@ template <bool kAllFit>
 __device__ __forceinline__ void prefetch_row(const DevPtrs& d, const RowK* lrows, const uint32_t* roff_s,
                                              const uint2* meta_s, uint32_t r, Prefetch& pf) {
   const uint32_t lane = threadIdx.x;
-  // wave-uniform row facts, so that the load count below is a scalar decision
-  pf.st.first = __builtin_amdgcn_readfirstlane(roff_s[r]);
-  pf.st.n = __builtin_amdgcn_readfirstlane(roff_s[r + 1]) - pf.st.first;
+  const uint32_t a = __builtin_amdgcn_readfirstlane(roff_s[r]);
+  const uint32_t n = __builtin_amdgcn_readfirstlane(roff_s[r + 1]) - a;
   const uint2 meta = meta_s[r];
   pf.st.meta = make_uint2(__builtin_amdgcn_readfirstlane(meta.x), __builtin_amdgcn_readfirstlane(meta.y));
   const RowK rk = lrows[r];   // the row's constants, for the step that uses the stage
   pf.st.rk = RowK{uniform_f(rk.x), uniform_f(rk.half_y), uniform_f(rk.y_lo), uniform_f(rk.inv_wy)};
-  pf.st.fits = kAllFit || pf.st.n <= (uint32_t)kStageHits;
+  pf.st.fits = kAllFit || n <= (uint32_t)kStageHits;
+  const uint32_t ybase = a & ~1u, ycnt = a + n - ybase;
+  pf.st.first = ybase;
+  const uint32_t bbase = pf.st.meta.x & ~3u;
+  pf.st.boff = pf.st.meta.x - bbase;
   if (!pf.st.fits) return;
-  if (pf.st.n > 0) {
-    const uint32_t last = pf.st.first + pf.st.n - 1;
+  const f32x4* ysrc = reinterpret_cast<const f32x4*>(d.syz + ybase);
 #pragma unroll
-    for (int m = 0; m < kPreYz; ++m)
-      if ((uint32_t)m * kThreads < pf.st.n) pf.yz[m] = d.syz[min(pf.st.first + lane + m * kThreads, last)];
+  for (int m = 0; m < kPreYz; ++m) {
+    const uint32_t q = lane + m * kThreads;   // pair q holds entries 2q, 2q + 1
+    pf.yz[m] = ysrc[2 * q < ycnt ? q : 0];
   }
-  const uint32_t nb1 = (pf.st.meta.y & 0xFFFFu) * (pf.st.meta.y >> 16) + 1;   // >= 2: every row has a grid
-  const uint32_t blast = pf.st.meta.x + nb1 - 1;
+  const uint32_t bcnt = pf.st.boff + (pf.st.meta.y & 0xFFFFu) * (pf.st.meta.y >> 16) + 1;   // every row has a grid
+  const u32x4* bsrc = reinterpret_cast<const u32x4*>(d.bin_start + bbase);
 #pragma unroll
-  for (int m = 0; m < kPreBs; ++m)
-    if ((uint32_t)m * kThreads < nb1) pf.bs[m] = d.bin_start[min(pf.st.meta.x + lane + m * kThreads, blast)];
+  for (int m = 0; m < kPreBs; ++m) {
+    const uint32_t q = lane + m * kThreads;   // quad q holds entries 4q .. 4q + 3
+    pf.bs[m] = bsrc[4 * q < bcnt ? q : 0];
+  }
 }
 
 // Write prefetched registers to the LDS stage (call between two barriers).
-// Slots past the row's end receive copies of its last entries and are never read.
-__device__ __forceinline__ void commit_row(const Prefetch& pf, float2* yz_s, uint32_t* bs_s, Stage& st) {
+__device__ __forceinline__ void commit_row(const Prefetch& pf, f32x4* yz4_s, u32x4* bs4_s, Stage& st) {
   const uint32_t lane = threadIdx.x;
   st = pf.st;
   if (!st.fits) return;
 #pragma unroll
-  for (int m = 0; m < kPreYz; ++m)
-    if ((uint32_t)m * kThreads < st.n) yz_s[lane + m * kThreads] = pf.yz[m];
-  const uint32_t nb1 = (st.meta.y & 0xFFFFu) * (st.meta.y >> 16) + 1;
+  for (int m = 0; m < kPreYz; ++m) yz4_s[lane + m * kThreads] = pf.yz[m];
 #pragma unroll
-  for (int m = 0; m < kPreBs; ++m)
-    if ((uint32_t)m * kThreads < nb1) bs_s[lane + m * kThreads] = pf.bs[m];
+  for (int m = 0; m < kPreBs; ++m) bs4_s[lane + m * kThreads] = pf.bs[m];
 }
 
 template <bool kAllFit>
 __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k) {
   __shared__ RowK lrows[kMaxRows];
-  __shared__ float2 yz_s[kPreYz * kThreads + kGroup];   // >= kStageHits, + slack for whole-group reads
-  __shared__ uint32_t bs_s[kPreBs * kThreads];   // >= kStageBins
+  __shared__ f32x4 yz4_s[kPreYz * kThreads];   // the staged row: (y, z) pairs
+  __shared__ u32x4 bs4_s[kPreBs * kThreads];   // and its bin starts
+  const float2* yz_s = reinterpret_cast<const float2*>(yz4_s);
+  const uint32_t* bs_s = reinterpret_cast<const uint32_t*>(bs4_s);
   __shared__ uint32_t roff_s[kMaxRows + 1];   // the current sector's row offsets
   __shared__ uint2 meta_s[kMaxRows];          // and grid words
   const uint32_t R = d.R, T = d.tcap, S = d.S;
@@ -648,6 +670,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
   if (xcd * per + blockIdx.x / kXcds >= vend) return;
   load_rows(d, lrows);
   unsigned long long my_steps = 0;
+  uint32_t prio = 0;   // s_setprio level of this wave (waves start at 0)
   for (uint32_t v = xcd * per + blockIdx.x / kXcds; v < vend; v += gridDim.x / kXcds) {
     // sector of wave v: last s with wave_off[s] <= v
     uint32_t lo = 0, hi = S;
@@ -709,7 +732,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
     uint32_t r = __builtin_amdgcn_readfirstlane(wave_min(up ? r0 + 1 : R));   // wave-uniform from here on
     if (r < R) {
       prefetch_row<kAllFit>(d, lrows, roff_s, meta_s, r, pf);
-      commit_row(pf, yz_s, bs_s, st);
+      commit_row(pf, yz4_s, bs4_s, st);
       __syncthreads();
     }
     int32_t hnext = (up && r <= rl && r > r0) ? H[(size_t)r * T] : -1;
@@ -720,7 +743,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
     // including the prefetch of the next row, which should overlap the step.
     __builtin_amdgcn_s_waitcnt(0);
     while (r < R && __any(up)) {
-      set_priority(2 * R - r);   // the rest of this sweep, then (about) the whole inward sweep
+      set_priority(2 * R - r, prio);   // the rest of this sweep, then (about) the whole inward sweep
       if (r + 1 < R) prefetch_row<kAllFit>(d, lrows, roff_s, meta_s, r + 1, pf);
       const int32_t hchain = hnext;
       hnext = (up && r + 1 <= rl && r + 1 > r0) ? H[(size_t)(r + 1) * T] : -1;
@@ -739,7 +762,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
             int32_t h = hchain;
             if (!chain) {
               float2 unused;
-              h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
+              h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s + st.boff, st.first, st.meta, rk, sc, t, k, zref, half)
                           : search(d, srb + r, rk, sc, t, k, zref, unused);
               H[(size_t)r * T] = h;
             }
@@ -759,7 +782,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
         }
       }
       __syncthreads();
-      if (r + 1 < R) commit_row(pf, yz_s, bs_s, st);
+      if (r + 1 < R) commit_row(pf, yz4_s, bs4_s, st);
       __syncthreads();
       ++r;
     }
@@ -787,13 +810,13 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
     int32_t rr = (int32_t)__builtin_amdgcn_readfirstlane(wave_max(down ? rout : 0)) - 1;
     if (rr >= 0) {
       prefetch_row<kAllFit>(d, lrows, roff_s, meta_s, (uint32_t)rr, pf);
-      commit_row(pf, yz_s, bs_s, st);
+      commit_row(pf, yz4_s, bs4_s, st);
       __syncthreads();
     }
     hnext = (down && rr >= (int32_t)r0 && rr < (int32_t)rout) ? H[(size_t)rr * T] : -1;
     __builtin_amdgcn_s_waitcnt(0);   // as before the outward sweep
     while (rr >= 0 && __any(down)) {
-      set_priority((uint32_t)rr);
+      set_priority((uint32_t)rr, prio);
       if (rr > 0) prefetch_row<kAllFit>(d, lrows, roff_s, meta_s, (uint32_t)rr - 1, pf);
       const int32_t hrow = hnext;
       hnext = (down && rr - 1 >= (int32_t)r0 && rr - 1 < (int32_t)rout) ? H[(size_t)(rr - 1) * T] : -1;
@@ -811,7 +834,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
             int32_t h = below ? -1 : hrow;
             float2 unused;
             if (h < 0)
-              h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s, st.first, st.meta, rk, sc, t, k, zref, half)
+              h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s + st.boff, st.first, st.meta, rk, sc, t, k, zref, half)
                           : search(d, srb + (uint32_t)rr, rk, sc, t, k, zref, unused);
             H[(size_t)rr * T] = h;
             if (h >= 0) {
@@ -828,7 +851,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
         }
       }
       __syncthreads();
-      if (rr > 0) commit_row(pf, yz_s, bs_s, st);
+      if (rr > 0) commit_row(pf, yz4_s, bs4_s, st);
       __syncthreads();
       --rr;
     }
