@@ -147,7 +147,8 @@ __device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst
     K1[i] = c0[i] * I01 + c1[i] * I11;
     t.p[i] += K0[i] * r0 + K1[i] * r1;
   }
-  // P = (I - K H) C, then C' = P (I - K H)^T + K V K^T on the lower triangle
+  // P = (I - K H) C, then C' = P (I - K H)^T + K V K^T on the lower triangle,
+  // grouped as C' = P + D K^T with D = K V - P H^T (columns 0 and 1 of P)
   float P[5][5];
 #pragma unroll
   for (int i = 0; i < 5; ++i)
@@ -156,11 +157,16 @@ __device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst
       const float cij = i >= j ? c[tri(i, j)] : c[tri(j, i)];
       P[i][j] = cij - K0[i] * c0[j] - K1[i] * c1[j];
     }
+  float D0[5], D1[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    D0[i] = K0[i] * k.vy - P[i][0];
+    D1[i] = K1[i] * k.vz - P[i][1];
+  }
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j)
-      c[tri(i, j)] = P[i][j] - P[i][0] * K0[j] - P[i][1] * K1[j] + K0[i] * k.vy * K0[j] + K1[i] * k.vz * K1[j];
+    for (int j = 0; j <= i; ++j) c[tri(i, j)] = P[i][j] + D0[i] * K0[j] + D1[i] * K1[j];
   chi2 += r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);
 }
 
