@@ -259,10 +259,16 @@ tpc_status tpc_debug_copy(tpc_tracker* t, int32_t what, void* host_dst, uint64_t
  * TPC_E_INVAL for other values or while a request is in flight. */
 tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule);
 
-/* Per-pass timing with HIP events on the tracker's stream. */
+/* Per-pass timing with HIP events on the tracker's stream, for later requests.
+ * pass_mask: bit p times pass p (TPC_N_PASSES passes, in the order below);
+ * 0 turns timing off, TPC_TIME_ALL_PASSES times every pass.  Each timed pass
+ * costs up to two event records on the stream, so a caller that needs one
+ * pass's time should time that pass alone. */
 #define TPC_N_PASSES 6     /* K1 grid, K2 neighbours, K3/K4 clean+starts, K5 tracklets, K6 select, output */
-tpc_status tpc_set_timing(tpc_tracker* t, int32_t enable);
-/* Milliseconds of each pass of the last completed request (needs timing on). */
+#define TPC_TIME_ALL_PASSES 0x3F
+tpc_status tpc_set_timing(tpc_tracker* t, int32_t pass_mask);
+/* Milliseconds of each pass of the last completed request; -1 for a pass
+ * that was not timed.  TPC_E_INVAL if timing was off for that request. */
 tpc_status tpc_get_pass_times(tpc_tracker* t, float* ms, int32_t n);
 
 #ifdef __cplusplus

@@ -110,7 +110,7 @@ class ScheduleTuner:
         if key not in self.cache:
             tr = self.tracker
             best, best_ms = None, float("inf")
-            tr.set_timing(True)
+            tr.set_timing(True, passes=("tracklets",))
             for cand in self.candidates:
                 tr.set_tracklet_schedule(cand)
                 ms = float("inf")

@@ -74,9 +74,11 @@ Layout layout_of(const Caps& k) {
     o += (bytes + kAlign - 1) / kAlign * kAlign;
     return at;
   };
+  // per-frame metadata, contiguous so that one copy from a pinned mirror fills it
   L.row_off = take((k.SRmax + 1) * 4);
-  L.rows = take((uint64_t)k.R * sizeof(RowConst));
+  L.tile_off = take((k.SRmax + 1) * 4);
   L.secs = take((uint64_t)k.Smax * sizeof(SectorConst));
+  L.rows = take((uint64_t)k.R * sizeof(RowConst));
   L.row_dims = take(k.SRmax * 4);
   L.row_meta = take(k.SRmax * 8);
   // + 4 and + 2 entries: the tracklet stage reads both in 16-byte units
@@ -93,7 +95,6 @@ Layout layout_of(const Caps& k) {
   L.start_pos = take(k.T * 4);
   L.start_sr = take(k.T * 4);
   L.wave_off = take(((uint64_t)k.Smax + 1) * 4);
-  L.tile_off = take((k.SRmax + 1) * 4);
   L.tile_sr = take((k.N / kLinkTile + k.SRmax + 1) * 4);   // sum of ceil(N_r / 64) <= N / 64 + SR
   L.tk_rowhit = take((uint64_t)k.R * k.T * 4);
   L.tk_info = take(4 * k.T * 4);
@@ -165,6 +166,7 @@ struct tpc_tracker {
   KfConst kc{};
   std::vector<RowConst> rows;
   // pinned host memory
+  char* h_frame = nullptr;   // pinned mirror of the row_off / tile_off / secs block
   uint32_t* h_row_off = nullptr;
   uint32_t* h_tile_off = nullptr;
   SectorConst* h_secs = nullptr;
@@ -172,8 +174,8 @@ struct tpc_tracker {
   char* h_out = nullptr;      // all outputs, laid out like the device outputs
   hipEvent_t done = nullptr;
   hipEvent_t ev[kPasses + 1] = {};
-  bool timing = false;
-  bool timed_last = false;
+  uint32_t timing = 0;   // mask of timed passes
+  uint32_t timed_last = 0;   // pass mask the last request was timed with
   // request state
   uint64_t next_id = 1, cur_id = 0;
   bool in_flight = false;
@@ -357,11 +359,12 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   d.max_tracks = (uint32_t)caps.MT;
   d.max_track_clusters = caps.MC;
   // pinned host buffers
-  if (hipHostMalloc((void**)&t->h_row_off, (caps.SRmax + 1) * 4) != hipSuccess ||
-      hipHostMalloc((void**)&t->h_tile_off, (caps.SRmax + 1) * 4) != hipSuccess ||
-      hipHostMalloc((void**)&t->h_secs, caps.Smax * sizeof(SectorConst)) != hipSuccess ||
+  if (hipHostMalloc((void**)&t->h_frame, lay.secs + caps.Smax * sizeof(SectorConst) - lay.row_off) != hipSuccess ||
       hipHostMalloc((void**)&t->h_hdr, sizeof(ResultHeader)) != hipSuccess)
     return cleanup(fail(TPC_E_NOMEM, "hipHostMalloc staging"));
+  t->h_row_off = (uint32_t*)t->h_frame;
+  t->h_tile_off = (uint32_t*)(t->h_frame + (lay.tile_off - lay.row_off));
+  t->h_secs = (SectorConst*)(t->h_frame + (lay.secs - lay.row_off));
   const uint64_t out_bytes = lay.out_ndf + caps.MT * 4 - lay.out_sector;
   if (hipHostMalloc((void**)&t->h_out, out_bytes) != hipSuccess)
     return cleanup(fail(TPC_E_NOMEM, "hipHostMalloc outputs"));
@@ -386,9 +389,7 @@ void tpc_tracker_destroy(tpc_tracker* t) {
   for (auto& e : t->ev)
     if (e) (void)hipEventDestroy(e);
   if (t->own_ws && t->ws) (void)hipFree(t->ws);
-  if (t->h_row_off) (void)hipHostFree(t->h_row_off);
-  if (t->h_tile_off) (void)hipHostFree(t->h_tile_off);
-  if (t->h_secs) (void)hipHostFree(t->h_secs);
+  if (t->h_frame) (void)hipHostFree(t->h_frame);
   if (t->h_hdr) (void)hipHostFree(t->h_hdr);
   if (t->h_out) (void)hipHostFree(t->h_out);
   if (t->own_stream && t->stream) (void)hipStreamDestroy(t->stream);
@@ -461,8 +462,6 @@ tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t*
     c.pad = 0;
   }
   hipStream_t st = t->stream;   // the previous request was released, so the staging buffers are free
-  HIP_TRY(hipMemcpyAsync((void*)d.row_off, t->h_row_off, (SR + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync((void*)d.secs, t->h_secs, S * sizeof(SectorConst), hipMemcpyHostToDevice, st));
   if (f->flags & TPC_IN_HOST) {
     d.y = (const float*)(t->ws + t->lay.in_y);
     d.z = (const float*)(t->ws + t->lay.in_z);
@@ -484,8 +483,10 @@ tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t*
     }
     t->h_tile_off[SR] = nt;
     d.n_link_tiles = nt;
-    HIP_TRY(hipMemcpyAsync((void*)d.tile_off, t->h_tile_off, (SR + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st));
   }
+  // row offsets, tile offsets and sector constants in one copy
+  HIP_TRY(hipMemcpyAsync((void*)d.row_off, t->h_frame, t->lay.secs + S * sizeof(SectorConst) - t->lay.row_off,
+                         hipMemcpyHostToDevice, st));
   // selector tile: 4 rows, or 2 when a 4-row block would need more than
   // kSelectTilePreferred words of LDS (fewer resident tiles), or 1 row up to
   // kSelectTileWords; 0 = rows too large, global-memory selector.  (Measured:
@@ -506,24 +507,29 @@ tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t*
     }
   }
   d.tile_cap = tile_cap;
-  const bool tm = t->timing;
-  if (tm) HIP_TRY(hipEventRecord(t->ev[0], st));
+  // event b opens pass b and closes pass b - 1: recorded when either is timed
+  const uint32_t tmask = t->timing;
+  auto mark = [&](int b) -> hipError_t {
+    const uint32_t need = (tmask >> b) | (b > 0 ? tmask >> (b - 1) : 0u);
+    return (need & 1u) ? hipEventRecord(t->ev[b], st) : hipSuccess;
+  };
+  HIP_TRY(mark(0));
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, st, d.hdr);
   launch_grid(d, max_row, st);
-  if (tm) HIP_TRY(hipEventRecord(t->ev[1], st));
+  HIP_TRY(mark(1));
   launch_links(d, max_row, st);
-  if (tm) HIP_TRY(hipEventRecord(t->ev[2], st));
+  HIP_TRY(mark(2));
   launch_clean_starts(d, max_row, st);
-  if (tm) HIP_TRY(hipEventRecord(t->ev[3], st));
+  HIP_TRY(mark(3));
   launch_tracklets(d, t->kc, max_row, st);
-  if (tm) HIP_TRY(hipEventRecord(t->ev[4], st));
+  HIP_TRY(mark(4));
   launch_select(d, t->kc, tile_rows, st);
-  if (tm) HIP_TRY(hipEventRecord(t->ev[5], st));
+  HIP_TRY(mark(5));
   HIP_TRY(hipMemcpyAsync(t->h_hdr, d.hdr, sizeof(ResultHeader), hipMemcpyDeviceToHost, st));
-  if (tm) HIP_TRY(hipEventRecord(t->ev[6], st));
+  HIP_TRY(mark(6));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(t->done, st));
-  t->timed_last = tm;
+  t->timed_last = tmask;
   t->cur_id = t->next_id++;
   t->in_flight = true;
   t->fetched = false;
@@ -668,9 +674,10 @@ tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule) {
   return TPC_OK;
 }
 
-tpc_status tpc_set_timing(tpc_tracker* t, int32_t enable) {
+tpc_status tpc_set_timing(tpc_tracker* t, int32_t pass_mask) {
   if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
-  t->timing = enable != 0;
+  if (pass_mask & ~TPC_TIME_ALL_PASSES) return fail(TPC_E_INVAL, "pass_mask has bits beyond the passes");
+  t->timing = (uint32_t)pass_mask;
   return TPC_OK;
 }
 
@@ -678,8 +685,11 @@ tpc_status tpc_get_pass_times(tpc_tracker* t, float* ms, int32_t n) {
   if (!t || !ms) return fail(TPC_E_INVAL, "NULL argument");
   if (!t->timed_last) return fail(TPC_E_INVAL, "timing was off for the last request");
   HIP_TRY(hipSetDevice(t->device));
-  HIP_TRY(hipEventSynchronize(t->ev[kPasses]));
-  for (int i = 0; i < n && i < kPasses; ++i) HIP_TRY(hipEventElapsedTime(&ms[i], t->ev[i], t->ev[i + 1]));
+  HIP_TRY(hipEventSynchronize(t->done));
+  for (int i = 0; i < n && i < kPasses; ++i) {
+    ms[i] = -1.0f;
+    if (t->timed_last >> i & 1u) HIP_TRY(hipEventElapsedTime(&ms[i], t->ev[i], t->ev[i + 1]));
+  }
   return TPC_OK;
 }
 

@@ -310,10 +310,17 @@ class Tracker:
         """0 auto, 1 one lane per tracklet, 2 row-synchronous (applies to later requests)."""
         _check(load().tpc_set_tracklet_schedule(self._h, int(schedule)))
 
-    def set_timing(self, on=True):
-        _check(load().tpc_set_timing(self._h, 1 if on else 0))
+    def set_timing(self, on=True, passes=None):
+        """Time every pass (or only the named ones, e.g. ("tracklets",)) of later requests."""
+        mask = 0
+        if on:
+            names = PASS_NAMES if passes is None else passes
+            for n in names:
+                mask |= 1 << PASS_NAMES.index(n)
+        _check(load().tpc_set_timing(self._h, mask))
 
     def pass_times(self):
+        """Milliseconds of the timed passes of the last request, by pass name."""
         ms = (C.c_float * N_PASSES)()
         _check(load().tpc_get_pass_times(self._h, ms, N_PASSES))
-        return dict(zip(PASS_NAMES, [float(v) for v in ms]))
+        return {n: float(v) for n, v in zip(PASS_NAMES, ms) if v >= 0.0}

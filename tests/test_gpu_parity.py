@@ -139,6 +139,26 @@ def test_determinism_and_host_input(torch_cuda):
             assert np.array_equal(getattr(a, f), getattr(x, f)), f
 
 
+def test_pass_timing_mask(torch_cuda):
+    """Timing selects passes; untimed passes are absent and results do not depend on it."""
+    from paper_2502_09138_amd.tracker import PASS_NAMES, TrackerError
+    ev = synth.single_sector(seed=4)
+    tr = _tracker(ev)
+    ref = tr.track_event(ev)
+    tr.set_timing(True)
+    out = tr.track_event(ev)
+    pt = tr.pass_times()
+    assert set(pt) == set(PASS_NAMES) and all(v >= 0.0 for v in pt.values())
+    tr.set_timing(True, passes=("tracklets",))
+    tr.track_event(ev)
+    assert set(tr.pass_times()) == {"tracklets"}
+    tr.set_timing(False)
+    tr.track_event(ev)
+    with pytest.raises(TrackerError):
+        tr.pass_times()
+    assert np.array_equal(ref.cluster_ids, out.cluster_ids) and np.array_equal(ref.param, out.param)
+
+
 def test_golden_straight_line_on_gpu(torch_cuda):
     import json, os
     from paper_2502_09138_amd.tracker import Tracker
