@@ -12,8 +12,9 @@
 // LDS:
 //   k_claim_tiles  every valid tracklet of the sector raises W_tile[hit] with an
 //                  LDS atomicMax; the tile is then written to W (coalesced) --
-//                  every position is written, so W needs no clearing;
-//   k_own_tiles    counts each tracklet's owned hits in the tile -> own_part;
+//                  every position is written, so W needs no clearing -- and,
+//                  from the same LDS copy, each tracklet's owned hits in the
+//                  tile are counted -> own_part;
 //   k_accept       sums the tiles, applies the acceptance rule, turns own_part
 //                  into per-tile prefixes and packs (owned << 32) | accepted for
 //                  one 64-bit scan giving track index and cluster offset;
@@ -23,7 +24,7 @@
 //   k_emit_tiles   walks the sector's tracks (not all its tracklets) and writes
 //                  the owned cluster ids of each at offset + prefix, row by row
 //                  (ascending row order);
-//   k_finish       totals and capacity flags.
+//   (k_records also writes the totals and capacity flags.)
 // Rows too large for an LDS tile use the same steps with W in global memory,
 // one thread per tracklet (k_claim_g / k_own_g / k_emit_g).
 #include "device_common.h"
@@ -74,14 +75,8 @@ __global__ void __launch_bounds__(kThreads) k_claim_tiles(DevPtrs d, KfConst k, 
   }
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) d.W[tl.first + j] = wt[j];
-}
-
-__global__ void __launch_bounds__(kThreads) k_own_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
-  extern __shared__ uint32_t wt[];
-  const Tile tl = tile_of(d, tile_rows, n_tiles);
-  const uint32_t T = d.tcap, tt = blockIdx.x % n_tiles;
-  for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) wt[j] = d.W[tl.first + j];
-  __syncthreads();
+  // every claim on the tile's rows is in: count each tracklet's owned hits here
+  const uint32_t tt = blockIdx.x % n_tiles;
   for (uint32_t i = tl.ts + threadIdx.x; i < tl.te; i += blockDim.x) {
     const int32_t nh = d.tk_info[i];
     uint32_t cnt = 0;
@@ -135,7 +130,7 @@ __global__ void __launch_bounds__(kThreads) k_emit_tiles(DevPtrs d, KfConst k, u
     const uint32_t i = d.acc_list[v];
     const unsigned long long pk = d.tk_pack[i];
     const unsigned long long co = d.tk_scan[i] >> 32;
-    if (co + (pk >> 32) > d.max_track_clusters) continue;   // flagged in k_finish
+    if (co + (pk >> 32) > d.max_track_clusters) continue;   // flagged by finish()
     const int32_t nh = d.tk_info[i];
     const int32_t a = max((int32_t)tl.ra, d.tk_info[T + i]), b = min((int32_t)tl.rb - 1, d.tk_info[2 * T + i]);
     if (a > b) continue;
@@ -148,8 +143,24 @@ __global__ void __launch_bounds__(kThreads) k_emit_tiles(DevPtrs d, KfConst k, u
   }
 }
 
+// Totals and capacity flags (one thread).
+__device__ __forceinline__ void finish(const DevPtrs& d) {
+  const uint32_t nt = n_tracklets(d);
+  const unsigned long long tot = d.tk_scan[nt];
+  uint32_t ntr = (uint32_t)(tot & 0xFFFFFFFFull);
+  unsigned long long ncl = tot >> 32;
+  uint32_t flags = 0;
+  if (ntr > d.max_tracks) flags |= 4u;
+  if (ncl > d.max_track_clusters) flags |= 8u;
+  if (flags) atomicOr(&d.hdr->error_flags, flags);
+  d.hdr->n_tracks = ntr;
+  d.hdr->n_track_clusters = ncl;
+  if (!flags) d.out_first[ntr] = (uint32_t)ncl;
+}
+
 __global__ void __launch_bounds__(kThreads) k_records(DevPtrs d, KfConst k) {
   const uint32_t nt = n_tracklets(d), T = d.tcap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) finish(d);
   const XcdSched sch = xcd_sched(nt);
   for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
     const uint32_t i = vb * blockDim.x + threadIdx.x;
@@ -159,7 +170,7 @@ __global__ void __launch_bounds__(kThreads) k_records(DevPtrs d, KfConst k) {
     const unsigned long long pre = d.tk_scan[i];
     const uint32_t ti = (uint32_t)(pre & 0xFFFFFFFFull);
     const unsigned long long co = pre >> 32;
-    if (ti >= d.max_tracks) continue;                          // flagged in k_finish
+    if (ti >= d.max_tracks) continue;                          // flagged by finish()
     d.acc_list[ti] = i;                                        // track -> tracklet, for the tiled emit
     if (co + (pk >> 32) > d.max_track_clusters) continue;
     const int32_t nh = d.tk_info[i];
@@ -249,19 +260,6 @@ __global__ void __launch_bounds__(kThreads) k_emit_g(DevPtrs d, KfConst k) {
   }
 }
 
-__global__ void k_finish(DevPtrs d) {
-  const uint32_t nt = n_tracklets(d);
-  const unsigned long long tot = d.tk_scan[nt];
-  uint32_t ntr = (uint32_t)(tot & 0xFFFFFFFFull);
-  unsigned long long ncl = tot >> 32;
-  uint32_t flags = 0;
-  if (ntr > d.max_tracks) flags |= 4u;
-  if (ncl > d.max_track_clusters) flags |= 8u;
-  if (flags) atomicOr(&d.hdr->error_flags, flags);
-  d.hdr->n_tracks = ntr;
-  d.hdr->n_track_clusters = ncl;
-  if (!flags) d.out_first[ntr] = (uint32_t)ncl;
-}
 
 }  // namespace
 
@@ -272,7 +270,6 @@ void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipSt
     const size_t lds = (size_t)d.tile_cap * sizeof(uint32_t);
     const dim3 tiles(d.S * n_tiles);
     hipLaunchKernelGGL(k_claim_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
-    hipLaunchKernelGGL(k_own_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
     hipLaunchKernelGGL(k_accept, dim3(blocks), dim3(kThreads), 0, s, d, k, tile_rows);
     launch_scan_u64(d.tk_pack, d.tk_scan, &d.hdr->n_starts, d.tcap, d.scan_blocks, s);
     hipLaunchKernelGGL(k_records, dim3(blocks), dim3(kThreads), 0, s, d, k);
@@ -286,7 +283,6 @@ void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipSt
     hipLaunchKernelGGL(k_emit_g, dim3(blocks), dim3(kThreads), 0, s, d, k);
     hipLaunchKernelGGL(k_records, dim3(blocks), dim3(kThreads), 0, s, d, k);
   }
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, d);
 }
 
 }  // namespace tpc

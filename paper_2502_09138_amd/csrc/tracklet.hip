@@ -185,6 +185,7 @@ __device__ __forceinline__ void set_c0(Trk& t, const KfConst& k) {
 // flat sequence of candidate groups per lane (see search_lds); the kGroup loads
 // of a group are issued together.
 constexpr int kGroup = 4;
+constexpr int kGroupLds = 4;   // the same for the LDS search
 
 __device__ __forceinline__ int32_t search_m(const DevPtrs& d, uint2 meta, const RowK& rk, const SectorConst& sc,
                                             const Trk& t, const KfConst& k, float zref, float2& hv) {
@@ -238,10 +239,10 @@ __device__ __forceinline__ int32_t search(const DevPtrs& d, uint32_t sr, const R
 // The same search over a row staged in LDS: (y, z) of the row's hits at
 // yz[q - first] and its bin starts (global positions) in bs[].  It is run by the
 // two lanes of a pair that carry the same tracklet: on every z-line they take
-// alternate groups of kGroup candidates, walking the z-lines as one flat
+// alternate groups of kGroupLds candidates, walking the z-lines as one flat
 // sequence, and then exchange their best candidates (a DPP swap inside the
 // pair, no LDS round trip).  A group is read whole: its entries past the
-// z-line's end (at most kGroup - 1, inside the stage's slack) are masked out.
+// z-line's end (at most kGroupLds - 1, inside the stage's slack) are masked out.
 // The result -- smallest deviation, ties to the smaller position -- is the same
 // as a single ascending scan.
 __device__ __forceinline__ int pair_swap(int v) {   // value of the other lane of the pair (quad_perm 1,0,3,2)
@@ -264,20 +265,20 @@ __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* 
   float bd = 0.0f;
   // the two lanes of a pair take alternate groups of every z-line
   int iz = iz0;
-  uint32_t q = bs[iz * ny + iy0] + half * kGroup, hi = bs[iz * ny + iy1 + 1];
+  uint32_t q = bs[iz * ny + iy0] + half * kGroupLds, hi = bs[iz * ny + iy1 + 1];
   for (;;) {
     while (q >= hi && iz < iz1) {
       ++iz;
-      q = bs[iz * ny + iy0] + half * kGroup;
+      q = bs[iz * ny + iy0] + half * kGroupLds;
       hi = bs[iz * ny + iy1 + 1];
     }
     if (q >= hi) break;
     const float2* g = yz + (q - first);
-    float2 h[kGroup];
+    float2 h[kGroupLds];
 #pragma unroll
-    for (int j = 0; j < kGroup; ++j) h[j] = g[j];
+    for (int j = 0; j < kGroupLds; ++j) h[j] = g[j];
 #pragma unroll
-    for (int j = 0; j < kGroup; ++j) {
+    for (int j = 0; j < kGroupLds; ++j) {
       const float dy = h[j].x - yp, dz = (h[j].y - zref) - zp;
       if (q + j < hi && fabsf(dy) <= wy && fabsf(dz) <= wz) {
         const float dd = dy * dy * isy + dz * dz * isz;
@@ -287,7 +288,7 @@ __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* 
         }
       }
     }
-    q += kPair * kGroup;
+    q += kPair * kGroupLds;
   }
   // the pair's two candidates: smaller deviation, ties to the smaller position
   const int32_t ob = pair_swap(best);
@@ -561,8 +562,8 @@ constexpr int kStageHits = 320;
 constexpr int kStageBins = kStageHits + 2;                       // nBins + 1 <= N_r + 1
 constexpr int kPreYz = 3;   // float4 loads per lane: 2 hits each
 constexpr int kPreBs = 2;   // uint4 loads per lane: 4 bin starts each
-// alignment slack (1), whole-group reads past a z-line (kGroup - 1)
-static_assert(kPreYz * kThreads * 2 >= kStageHits + 1 + kGroup - 1, "yz stage too small");
+// alignment slack (1), whole-group reads past a z-line (kGroupLds - 1)
+static_assert(kPreYz * kThreads * 2 >= kStageHits + 1 + kGroupLds - 1, "yz stage too small");
 static_assert(kPreBs * kThreads * 4 >= kStageBins + 3, "bin stage too small");
 
 struct Stage {
