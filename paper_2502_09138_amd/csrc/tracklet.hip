@@ -66,19 +66,24 @@ __device__ __forceinline__ float asin_over_prime(float u) {
 }
 
 // Helix transport from x to x + dx with covariance; false on |sin phi| >= s_max or |u| >= 1.
+// kNoExit: the failure tests do not branch (the row-synchronous waves, where a
+// branch costs every lane); on false the state then holds meaningless values,
+// and every caller stops the tracklet without reading it again.
+template <bool kNoExit>
 __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
   const float s1 = t.p[2], tl = t.p[3], qp = t.p[4];
   const float kap = k.bk * qp;
-  if (!(fabsf(s1) < k.s_max)) return false;
+  if (!kNoExit && !(fabsf(s1) < k.s_max)) return false;
   const float s2 = s1 + kap * dx;
-  if (!(fabsf(s2) < k.s_max)) return false;
+  if (!kNoExit && !(fabsf(s2) < k.s_max)) return false;
   const float c1 = fsqrt((1.0f - s1) * (1.0f + s1));
   const float c2 = fsqrt((1.0f - s2) * (1.0f + s2));
   const float ic = frcp(c1 + c2);
   const float dy = dx * ((s1 + s2) * ic);
   const float L = fsqrt(dx * dx + dy * dy);
   const float u = 0.5f * kap * L;
-  if (!(fabsf(u) < 1.0f)) return false;
+  if (!kNoExit && !(fabsf(u) < 1.0f)) return false;
+  const bool ok = fabsf(s1) < k.s_max && fabsf(s2) < k.s_max && fabsf(u) < 1.0f;
   const float sgn = dx >= 0.0f ? 1.0f : -1.0f;
   const float S = sgn * L * asin_over(u);
   // Jacobian entries (exact derivative of the map above)
@@ -124,7 +129,7 @@ __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
 #pragma unroll
     for (int j = 0; j <= i; ++j) c[tri(i, j)] = rr[j];
   }
-  return true;
+  return ok;
 }
 
 // Kalman update with a measurement of (y, z), Joseph form.
@@ -263,32 +268,36 @@ __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* 
   const int iz1 = bin1((za + wz) + kWinPad, sc.z_lo, sc.inv_wz, nz);
   int32_t best = -1;
   float bd = 0.0f;
-  // the two lanes of a pair take alternate groups of every z-line
-  int iz = iz0;
-  uint32_t q = bs[iz * ny + iy0] + half * kGroupLds, hi = bs[iz * ny + iy1 + 1];
-  for (;;) {
-    while (q >= hi && iz < iz1) {
-      ++iz;
-      q = bs[iz * ny + iy0] + half * kGroupLds;
-      hi = bs[iz * ny + iy1 + 1];
-    }
-    if (q >= hi) break;
-    const float2* g = yz + (q - first);
-    float2 h[kGroupLds];
+  // z-lines are taken two at a time (a window almost never spans more): the
+  // candidates of the pair of lines form one flat sequence -- line iz, then
+  // line iz + 1, so positions ascend -- and the two lanes of a pair take
+  // alternate groups of it
+  for (int iz = iz0; iz <= iz1; iz += 2) {
+    const int izb = iz + 1 <= iz1 ? iz + 1 : iz;
+    const uint32_t lo0 = bs[iz * ny + iy0], hi0 = bs[iz * ny + iy1 + 1];
+    const uint32_t lo1 = bs[izb * ny + iy0], hi1 = bs[izb * ny + iy1 + 1];
+    const uint32_t n0 = hi0 - lo0, tot = n0 + (izb > iz ? hi1 - lo1 : 0u);
+    for (uint32_t g0 = half * kGroupLds; g0 < tot; g0 += kPair * kGroupLds) {
+      uint32_t pos[kGroupLds];
+      float2 h[kGroupLds];
 #pragma unroll
-    for (int j = 0; j < kGroupLds; ++j) h[j] = g[j];
+      for (int j = 0; j < kGroupLds; ++j) {
+        const uint32_t f = g0 + j;   // past the end: at most kGroupLds - 1 entries beyond a line, masked below
+        pos[j] = f < n0 ? lo0 + f : lo1 + (f - n0);
+        h[j] = yz[pos[j] - first];
+      }
 #pragma unroll
-    for (int j = 0; j < kGroupLds; ++j) {
-      const float dy = h[j].x - yp, dz = (h[j].y - zref) - zp;
-      if (q + j < hi && fabsf(dy) <= wy && fabsf(dz) <= wz) {
-        const float dd = dy * dy * isy + dz * dz * isz;
-        if (best < 0 || dd < bd) {
-          best = (int32_t)(q + j);
-          bd = dd;
+      for (int j = 0; j < kGroupLds; ++j) {
+        const float dy = h[j].x - yp, dz = (h[j].y - zref) - zp;
+        if (g0 + j < tot && fabsf(dy) <= wy && fabsf(dz) <= wz) {
+          const float dd = dy * dy * isy + dz * dz * isz;
+          if (best < 0 || dd < bd) {
+            best = (int32_t)pos[j];
+            bd = dd;
+          }
         }
       }
     }
-    q += kPair * kGroupLds;
   }
   // the pair's two candidates: smaller deviation, ties to the smaller position
   const int32_t ob = pair_swap(best);
@@ -440,7 +449,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
       const float2 h = hnx;
       if (r + 1 <= rl) hnx = d.syz[H[(size_t)(r + 1) * T]];
       const float x = lrows[r].x;
-      if (!propagate(t, x - xprev, k)) {
+      if (!propagate<false>(t, x - xprev, k)) {
         ok = false;
         break;
       }
@@ -464,7 +473,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
       if (r + 1 < R) mnx = d.row_meta[srb + r + 1];
       const RowK rk = lrows[r];
       ++steps;
-      if (!propagate(t, rk.x - xprev, k)) break;
+      if (!propagate<false>(t, rk.x - xprev, k)) break;
       xprev = rk.x;
       if (fabsf(t.p[0]) > rk.half_y + k.margin) break;
       float2 hm = make_float2(0.0f, 0.0f);
@@ -511,7 +520,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
       if (r >= 1) mA = d.row_meta[srb + (uint32_t)r - 1];
       const RowK rk = lrows[r];
       ++steps;
-      if (!propagate(t, rk.x - xprev, k)) break;
+      if (!propagate<false>(t, rk.x - xprev, k)) break;
       xprev = rk.x;
       const bool below = (uint32_t)r < r0;
       if (below && fabsf(t.p[0]) > rk.half_y + k.margin) break;
@@ -758,7 +767,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
         const RowK rk = st.rk;
         const bool chain = r <= rl;
         if (!chain) ++steps;
-        if (!propagate(t, rk.x - xprev, k)) {
+        if (!propagate<true>(t, rk.x - xprev, k)) {
           up = false;
           failed = chain;
         } else {
@@ -830,7 +839,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
       if (down && rr < (int32_t)rout) {
         const RowK rk = st.rk;
         ++steps;
-        if (!propagate(t, rk.x - xprev, k)) {
+        if (!propagate<true>(t, rk.x - xprev, k)) {
           down = false;
         } else {
           xprev = rk.x;
