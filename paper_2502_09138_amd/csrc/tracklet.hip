@@ -666,8 +666,10 @@ __device__ __forceinline__ void commit_row(const Prefetch& pf, f32x4* yz4_s, u32
   for (int m = 0; m < kPreBs; ++m) bs4_s[lane + m * kThreads] = pf.bs[m];
 }
 
+// Three waves per SIMD (<= 168 VGPRs) keep every wave of a central event
+// resident at once.
 template <bool kAllFit>
-__global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) k_tracklets_rs(DevPtrs d, KfConst k) {
   __shared__ RowK lrows[kMaxRows];
   __shared__ f32x4 yz4_s[kPreYz * kThreads];   // the staged row: (y, z) pairs
   __shared__ u32x4 bs4_s[kPreBs * kThreads];   // and its bin starts
@@ -764,38 +766,36 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
       const int32_t hchain = hnext;
       hnext = (up && r + 1 <= rl && r + 1 > r0) ? H[(size_t)(r + 1) * T] : -1;
       if (up && r > r0) {
+        // flags instead of nested branches: a lane that stops here keeps
+        // nothing of this step (its state is not read again)
         const RowK rk = st.rk;
         const bool chain = r <= rl;
-        if (!chain) ++steps;
-        if (!propagate<true>(t, rk.x - xprev, k)) {
-          up = false;
-          failed = chain;
-        } else {
-          xprev = rk.x;
-          if (!chain && fabsf(t.p[0]) > rk.half_y + k.margin) {
-            up = false;
-          } else {
-            int32_t h = hchain;
-            if (!chain) {
-              float2 unused;
-              h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s + st.boff, st.first, st.meta, rk, sc, t, k, zref, half)
-                          : search(d, srb + r, rk, sc, t, k, zref, unused);
-              H[(size_t)r * T] = h;
-            }
-            if (h >= 0) {
-              const float2 hm = (kAllFit || st.fits) ? yz_s[(uint32_t)h - st.first] : d.syz[h];
-              update(t, hm.x, hm.y - zref, k, chi2);
-              if (r >= rl) {
+        steps += chain ? 0u : 1u;
+        const bool pok = propagate<true>(t, rk.x - xprev, k);
+        xprev = rk.x;
+        failed = failed || (!pok && chain);
+        const bool go = pok && (chain || fabsf(t.p[0]) <= rk.half_y + k.margin);
+        up = go;
+        int32_t h = hchain;
+        if (go && !chain) {
+          float2 unused;
+          h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s + st.boff, st.first, st.meta, rk, sc, t, k, zref, half)
+                                   : search(d, srb + r, rk, sc, t, k, zref, unused);
+          H[(size_t)r * T] = h;
+        }
+        if (go && h >= 0) {
+          const float2 hm = (kAllFit || st.fits) ? yz_s[(uint32_t)h - st.first] : d.syz[h];
+          update(t, hm.x, hm.y - zref, k, chi2);
+          if (r >= rl) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
-                rout = r;
-                miss = 0;
-              }
-            } else if (++miss > k.max_miss) {
-              up = false;
-            }
+            for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
+            rout = r;
+            miss = 0;
           }
         }
+        const bool missed = go && h < 0;
+        miss += missed ? 1 : 0;
+        up = up && !(missed && miss > k.max_miss);
       }
       __syncthreads();
       if (r + 1 < R) commit_row(pf, yz4_s, bs4_s, st);
@@ -837,34 +837,31 @@ __global__ void __launch_bounds__(kThreads) k_tracklets_rs(DevPtrs d, KfConst k)
       const int32_t hrow = hnext;
       hnext = (down && rr - 1 >= (int32_t)r0 && rr - 1 < (int32_t)rout) ? H[(size_t)(rr - 1) * T] : -1;
       if (down && rr < (int32_t)rout) {
-        const RowK rk = st.rk;
+        const RowK rk = st.rk;   // flags instead of nested branches, as in the outward sweep
         ++steps;
-        if (!propagate<true>(t, rk.x - xprev, k)) {
-          down = false;
-        } else {
-          xprev = rk.x;
-          const bool below = (uint32_t)rr < r0;
-          if (below && fabsf(t.p[0]) > rk.half_y + k.margin) {
-            down = false;
-          } else {
-            int32_t h = below ? -1 : hrow;
-            float2 unused;
-            if (h < 0)
-              h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s + st.boff, st.first, st.meta, rk, sc, t, k, zref, half)
-                          : search(d, srb + (uint32_t)rr, rk, sc, t, k, zref, unused);
-            H[(size_t)rr * T] = h;
-            if (h >= 0) {
-              const float2 hm = (kAllFit || st.fits) ? yz_s[(uint32_t)h - st.first] : d.syz[h];
-              update(t, hm.x, hm.y - zref, k, chi2);
-              ++nh;
-              snap = t;
-              rin = (uint32_t)rr;
-              if (below) miss = 0;
-            } else if (below && ++miss > k.max_miss) {
-              down = false;
-            }
-          }
+        const bool pok = propagate<true>(t, rk.x - xprev, k);
+        xprev = rk.x;
+        const bool below = (uint32_t)rr < r0;
+        const bool go = pok && !(below && fabsf(t.p[0]) > rk.half_y + k.margin);
+        down = go;
+        int32_t h = below ? -1 : hrow;
+        if (go && h < 0) {
+          float2 unused;
+          h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s + st.boff, st.first, st.meta, rk, sc, t, k, zref, half)
+                                   : search(d, srb + (uint32_t)rr, rk, sc, t, k, zref, unused);
         }
+        if (go) H[(size_t)rr * T] = h;
+        if (go && h >= 0) {
+          const float2 hm = (kAllFit || st.fits) ? yz_s[(uint32_t)h - st.first] : d.syz[h];
+          update(t, hm.x, hm.y - zref, k, chi2);
+          ++nh;
+          snap = t;
+          rin = (uint32_t)rr;
+          if (below) miss = 0;
+        }
+        const bool missed = go && below && h < 0;
+        miss += missed ? 1 : 0;
+        down = down && !(missed && miss > k.max_miss);
       }
       __syncthreads();
       if (rr > 0) commit_row(pf, yz4_s, bs4_s, st);
