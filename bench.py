@@ -36,7 +36,7 @@ K2_BYTES_PER_CLUSTER = 18.0     # read own (y, z) + each adjacent row once + bin
 # rocprofv3 --pmc passes of this script (commands and tables in profiles/), valid for the kernel sources
 # with these SHA-1 digests; reported as null once a source differs.
 PMC_SOURCES = {
-    "paper_2502_09138_amd/csrc/tracklet.hip": "88738e057f136c08ee7ed2d23040431122436376",
+    "paper_2502_09138_amd/csrc/tracklet.hip": "9c3577455dca9f2f8edf1243157739ae9b8756e3",
     "paper_2502_09138_amd/csrc/links.hip": "ad6bcd87cc9f7c3f0839ae36deca241dbd83786b",
     "paper_2502_09138_amd/csrc/grid.hip": "6460655febd2a7f572bd7741e338bdc971bf3f8e",
     "paper_2502_09138_amd/csrc/device_common.h": "b4b103e57db5db269528a9bdae40217f2bb52ff1",
@@ -44,9 +44,9 @@ PMC_SOURCES = {
 }
 MIB = float(1 << 20)
 PMC_TRAFFIC = {   # workload -> pass -> (fetch MiB, write MiB) per launch
-    "central_event": {"tracklets": (65.97, 90.03), "grid": (11.69, 18.10), "neighbours": (40.79, 10.98)},
-    "time_frame": {"tracklets": (7234.72, 1853.86), "grid": (84.84, 135.91), "neighbours": (367.69, 84.48)},
-    "uneven_chunks": {"tracklets": (11952.73, 5479.44), "grid": (166.96, 260.15), "neighbours": (829.08, 158.48)},
+    "central_event": {"tracklets": (65.42, 89.77), "grid": (11.69, 18.10), "neighbours": (40.79, 10.98)},
+    "time_frame": {"tracklets": (7256.53, 1852.76), "grid": (85.07, 135.93), "neighbours": (367.63, 84.48)},
+    "uneven_chunks": {"tracklets": (11965.04, 5476.65), "grid": (166.74, 260.15), "neighbours": (828.96, 158.48)},
 }
 
 
