@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--serve", type=float, default=0.0,
                     help="instead of the plain bench: serve a Poisson trace of this many seconds with one slot (plain "
                          "path) and with --slots slots, report p50/p99 latency and clusters/s of both")
-    ap.add_argument("--slots", type=int, default=3)
+    ap.add_argument("--slots", type=int, default=6)
     ap.add_argument("--rate", type=float, default=800.0, help="trace arrival rate (requests/s) for --serve")
     args = ap.parse_args()
     if args.gpus != 1:

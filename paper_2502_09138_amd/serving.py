@@ -75,7 +75,7 @@ def make_trace(pool, rate_hz, duration_s, pp_fraction=0.8, seed=5):
 
 
 class Server:
-    def __init__(self, max_clusters, max_sectors=36, slots=3, hbm_budget_bytes=200 << 30, cfg=None):
+    def __init__(self, max_clusters, max_sectors=36, slots=6, hbm_budget_bytes=200 << 30, cfg=None):
         cfg = cfg or default_config()
         probe = Tracker(cfg, max_clusters=max_clusters, max_sectors=max_sectors)
         per_slot = probe.workspace_bytes
