@@ -338,7 +338,7 @@ def main():
                            algorithmic_bytes=round(K2_BYTES_PER_CLUSTER * N), kernel_ms=round(pass_ms["neighbours"], 4)),
     }
     rec = {
-        "metric": "TPC clusters/s tracked at 1 GPU (plain path) + p50/p99 time-frame latency",
+        "metric": "TPC clusters/sec tracked at 1 GPU + p50/p99 time-frame latency vs plain path",
         "value": round(value, 1),
         "unit": "clusters/s",
         "n_gpus": 1,
