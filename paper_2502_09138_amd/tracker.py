@@ -57,9 +57,10 @@ class _Config(C.Structure):
 
 class _Frame(C.Structure):
     _fields_ = [
-        ("n_sectors", C.c_uint32), ("n_rows", C.c_uint32), ("row_offsets", C.POINTER(C.c_uint32)),
+        # pointer fields as plain addresses (the C side sees the same layout)
+        ("n_sectors", C.c_uint32), ("n_rows", C.c_uint32), ("row_offsets", C.c_void_p),
         ("y", C.c_void_p), ("z", C.c_void_p), ("charge", C.c_void_p), ("n_clusters", C.c_uint64),
-        ("sector_z_lo", C.POINTER(C.c_float)), ("sector_z_hi", C.POINTER(C.c_float)), ("flags", C.c_uint32),
+        ("sector_z_lo", C.c_void_p), ("sector_z_hi", C.c_void_p), ("flags", C.c_uint32),
     ]
 
 
@@ -192,6 +193,7 @@ class Tracker:
         c.workspace_bytes = nbytes
         # the tracker's own stream (default priority); each submit orders it after torch's current stream
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self._ready = torch.cuda.Event()   # reused to order each submit after torch's current stream
         c.stream = self.stream.cuda_stream
         self._h = C.c_void_p()
         _check(L.tpc_tracker_create(C.byref(c), C.byref(self._h)))
@@ -218,10 +220,10 @@ class Tracker:
         f = _Frame()
         f.n_rows = self.R
         f.n_sectors = (len(row_offsets) - 1) // self.R
-        f.row_offsets = row_offsets.ctypes.data_as(C.POINTER(C.c_uint32))
+        f.row_offsets = row_offsets.ctypes.data
         f.n_clusters = int(row_offsets[-1])
-        f.sector_z_lo = z_lo.ctypes.data_as(C.POINTER(C.c_float))
-        f.sector_z_hi = z_hi.ctypes.data_as(C.POINTER(C.c_float))
+        f.sector_z_lo = z_lo.ctypes.data
+        f.sector_z_hi = z_hi.ctypes.data
         if host:
             y = np.ascontiguousarray(y, np.float32)
             z = np.ascontiguousarray(z, np.float32)
@@ -233,7 +235,8 @@ class Tracker:
             # ordered after the work that produced y and z; the tensors stay referenced
             # (self._inputs) until release(), which waits for the request, so the
             # caching allocator cannot hand their memory out while the kernels read it
-            self.stream.wait_stream(self._torch.cuda.current_stream(self.device))
+            self._ready.record(self._torch.cuda.current_stream(self.device))
+            self.stream.wait_event(self._ready)
             f.y, f.z = y.data_ptr(), z.data_ptr()
             f.flags = TPC_IN_DEVICE
         self._inputs = (y, z, row_offsets, z_lo, z_hi)   # borrowed until the request completes
