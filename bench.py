@@ -36,7 +36,7 @@ K2_BYTES_PER_CLUSTER = 18.0     # read own (y, z) + each adjacent row once + bin
 # rocprofv3 --pmc passes of this script (commands and tables in profiles/), valid for the kernel sources
 # with these SHA-1 digests; reported as null once a source differs.
 PMC_SOURCES = {
-    "paper_2502_09138_amd/csrc/tracklet.hip": "9c3577455dca9f2f8edf1243157739ae9b8756e3",
+    "paper_2502_09138_amd/csrc/tracklet.hip": "04da676727566285dd7ca194c22faebfb6e4efa5",
     "paper_2502_09138_amd/csrc/links.hip": "ad6bcd87cc9f7c3f0839ae36deca241dbd83786b",
     "paper_2502_09138_amd/csrc/grid.hip": "6460655febd2a7f572bd7741e338bdc971bf3f8e",
     "paper_2502_09138_amd/csrc/device_common.h": "b4b103e57db5db269528a9bdae40217f2bb52ff1",

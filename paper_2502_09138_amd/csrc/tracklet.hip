@@ -550,8 +550,9 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
 // Row-synchronous schedule ("coalesced row-grid reads").  A wave takes up to
 // 32 tracklets of ONE sector, two lanes per tracklet: the pair splits each
 // candidate search and runs the rest of the step redundantly, which shortens
-// the wave's per-row instruction stream (a wave's critical path, not the SIMD's
-// throughput, bounds this kernel: about one wave per SIMD is resident).  After
+// the wave's per-row instruction stream (the longest waves' instruction issue
+// bounds this kernel: a central event's waves are all resident, 2-3 per SIMD,
+// and the SIMD favours those with the most rows still to step through).  After
 // each pair has walked its chain and built its seed, the wave sweeps the rows
 // in lockstep -- outward, then inward --
 // and at every row stages that row's (y, z) and bin starts in LDS with one
