@@ -57,38 +57,75 @@ __device__ __forceinline__ Tile tile_of(const DevPtrs& d, uint32_t tile_rows, ui
   return t;
 }
 
+// A thread takes kBatch of the sector's tracklets at a time and issues all
+// their loads (tracklet info, then the tile's rows of each) before using any,
+// so a tile's loop over the tracklets is not one dependent load chain per
+// tracklet.  Tiles have at most kTileRowsMax rows.
+constexpr int kBatch = 4;
+constexpr int kTileRowsMax = 4;
+
+struct TileHits {
+  int32_t h[kBatch][kTileRowsMax];   // hit in tile row ra + rr, -1 if none or outside [rin, rout]
+  uint32_t key[kBatch];
+};
+
+__device__ __forceinline__ void tile_hits(const DevPtrs& d, const KfConst& k, const Tile& tl, uint32_t i0,
+                                          TileHits& th) {
+  const uint32_t T = d.tcap;
+  int32_t nh[kBatch], rin[kBatch], rout[kBatch];
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    const uint32_t i = i0 + u * kThreads;
+    const bool in = i < tl.te;
+    nh[u] = in ? d.tk_info[i] : 0;
+    rin[u] = in ? d.tk_info[T + i] : 0;
+    rout[u] = in ? d.tk_info[2 * T + i] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    const uint32_t i = i0 + u * kThreads;
+    const bool ok = i < tl.te && nh[u] >= k.min_tracklet_hits;
+    const int32_t lo = max((int32_t)tl.ra, rin[u]), hi = min((int32_t)tl.rb - 1, rout[u]);
+    th.key[u] = key32((uint32_t)nh[u], i);
+#pragma unroll
+    for (int rr = 0; rr < kTileRowsMax; ++rr) {
+      const int32_t r = (int32_t)tl.ra + rr;
+      th.h[u][rr] = (ok && r >= lo && r <= hi) ? d.tk_rowhit[(size_t)r * T + i] : -1;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kThreads) k_claim_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
   extern __shared__ uint32_t wt[];
   const Tile tl = tile_of(d, tile_rows, n_tiles);
   const uint32_t T = d.tcap;
   for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) wt[j] = 0u;
   __syncthreads();
-  for (uint32_t i = tl.ts + threadIdx.x; i < tl.te; i += blockDim.x) {
-    const int32_t nh = d.tk_info[i];
-    if (nh < k.min_tracklet_hits) continue;
-    const int32_t a = max((int32_t)tl.ra, d.tk_info[T + i]), b = min((int32_t)tl.rb - 1, d.tk_info[2 * T + i]);
-    const uint32_t key = key32((uint32_t)nh, i);
-    for (int32_t r = a; r <= b; ++r) {
-      const int32_t h = d.tk_rowhit[(size_t)r * T + i];
-      if (h >= 0) atomicMax(&wt[(uint32_t)h - tl.first], key);
-    }
+  for (uint32_t i0 = tl.ts + threadIdx.x; i0 < tl.te; i0 += kBatch * kThreads) {
+    TileHits th;
+    tile_hits(d, k, tl, i0, th);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int rr = 0; rr < kTileRowsMax; ++rr)
+        if (th.h[u][rr] >= 0) atomicMax(&wt[(uint32_t)th.h[u][rr] - tl.first], th.key[u]);
   }
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) d.W[tl.first + j] = wt[j];
   // every claim on the tile's rows is in: count each tracklet's owned hits here
   const uint32_t tt = blockIdx.x % n_tiles;
-  for (uint32_t i = tl.ts + threadIdx.x; i < tl.te; i += blockDim.x) {
-    const int32_t nh = d.tk_info[i];
-    uint32_t cnt = 0;
-    if (nh >= k.min_tracklet_hits) {
-      const int32_t a = max((int32_t)tl.ra, d.tk_info[T + i]), b = min((int32_t)tl.rb - 1, d.tk_info[2 * T + i]);
-      const uint32_t key = key32((uint32_t)nh, i);
-      for (int32_t r = a; r <= b; ++r) {
-        const int32_t h = d.tk_rowhit[(size_t)r * T + i];
-        cnt += (h >= 0 && wt[(uint32_t)h - tl.first] == key) ? 1u : 0u;
-      }
+  for (uint32_t i0 = tl.ts + threadIdx.x; i0 < tl.te; i0 += kBatch * kThreads) {
+    TileHits th;
+    tile_hits(d, k, tl, i0, th);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const uint32_t i = i0 + u * kThreads;
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int rr = 0; rr < kTileRowsMax; ++rr)
+        cnt += (th.h[u][rr] >= 0 && wt[(uint32_t)th.h[u][rr] - tl.first] == th.key[u]) ? 1u : 0u;
+      if (i < tl.te) d.own_part[(size_t)tt * T + i] = (uint8_t)cnt;
     }
-    d.own_part[(size_t)tt * T + i] = (uint8_t)cnt;
   }
 }
 
@@ -265,7 +302,7 @@ __global__ void __launch_bounds__(kThreads) k_emit_g(DevPtrs d, KfConst k) {
 
 void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipStream_t s) {
   const uint32_t blocks = xcd_grid(std::min<uint32_t>(8192, std::max<uint32_t>(1, (d.tcap + kThreads - 1) / kThreads)));
-  if (tile_rows > 0 && d.S > 0) {
+  if (tile_rows > 0 && tile_rows <= (uint32_t)kTileRowsMax && d.S > 0) {
     const uint32_t n_tiles = (d.R + tile_rows - 1) / tile_rows;
     const size_t lds = (size_t)d.tile_cap * sizeof(uint32_t);
     const dim3 tiles(d.S * n_tiles);
