@@ -129,6 +129,8 @@ __global__ void __launch_bounds__(kThreads) k_claim_tiles(DevPtrs d, KfConst k, 
   }
 }
 
+constexpr int kAcceptBatch = 8;
+
 __global__ void __launch_bounds__(kThreads) k_accept(DevPtrs d, KfConst k, uint32_t tile_rows) {
   const uint32_t nt = n_tracklets(d), T = d.tcap;
   const XcdSched sch = xcd_sched(nt);
@@ -141,10 +143,16 @@ __global__ void __launch_bounds__(kThreads) k_accept(DevPtrs d, KfConst k, uint3
       // owned hits lie only in the tiles that overlap [rin, rout]
       const uint32_t t0 = (uint32_t)d.tk_info[T + i] / tile_rows, t1 = (uint32_t)d.tk_info[2 * T + i] / tile_rows;
       uint32_t owned = 0;
-      for (uint32_t tt = t0; tt <= t1; ++tt) {
-        const uint32_t c = d.own_part[(size_t)tt * T + i];
-        d.own_part[(size_t)tt * T + i] = (uint8_t)owned;   // prefix before this tile
-        owned += c;
+      for (uint32_t tb = t0; tb <= t1; tb += kAcceptBatch) {   // the batch's loads go out before its stores
+        uint32_t c[kAcceptBatch];
+#pragma unroll
+        for (int j = 0; j < kAcceptBatch; ++j) c[j] = tb + j <= t1 ? d.own_part[(size_t)(tb + j) * T + i] : 0u;
+#pragma unroll
+        for (int j = 0; j < kAcceptBatch; ++j)
+          if (tb + j <= t1) {
+            d.own_part[(size_t)(tb + j) * T + i] = (uint8_t)owned;   // prefix before this tile
+            owned += c[j];
+          }
       }
       const float need = k.min_owned_frac * (float)nh;
       if ((int32_t)owned >= k.min_track_hits && (float)owned >= need)
@@ -163,20 +171,49 @@ __global__ void __launch_bounds__(kThreads) k_emit_tiles(DevPtrs d, KfConst k, u
   const uint32_t v0 = (uint32_t)(d.tk_scan[tl.ts] & 0xFFFFFFFFull);
   const uint32_t v1 = min((uint32_t)(d.tk_scan[tl.te] & 0xFFFFFFFFull), d.max_tracks);
   __syncthreads();
-  for (uint32_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
-    const uint32_t i = d.acc_list[v];
-    const unsigned long long pk = d.tk_pack[i];
-    const unsigned long long co = d.tk_scan[i] >> 32;
-    if (co + (pk >> 32) > d.max_track_clusters) continue;   // flagged by finish()
-    const int32_t nh = d.tk_info[i];
-    const int32_t a = max((int32_t)tl.ra, d.tk_info[T + i]), b = min((int32_t)tl.rb - 1, d.tk_info[2 * T + i]);
-    if (a > b) continue;
-    const uint32_t key = key32((uint32_t)nh, i);
-    uint32_t o = (uint32_t)co + d.own_part[(size_t)tt * T + i];
-    for (int32_t r = a; r <= b; ++r) {
-      const int32_t h = d.tk_rowhit[(size_t)r * T + i];
-      if (h >= 0 && wt[(uint32_t)h - tl.first] == key) d.out_clusters[o++] = d.sid[h];
+  // kBatch tracks per thread at a time, each stage's loads issued together
+  for (uint32_t vb = v0 + threadIdx.x; vb < v1; vb += kBatch * kThreads) {
+    uint32_t i[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) i[u] = vb + u * kThreads < v1 ? d.acc_list[vb + u * kThreads] : 0u;
+    bool go[kBatch];
+    uint32_t o[kBatch], key[kBatch];
+    int32_t lo[kBatch], hi[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const bool in = vb + u * kThreads < v1;
+      const unsigned long long pk = in ? d.tk_pack[i[u]] : 0ull;
+      const unsigned long long co = in ? d.tk_scan[i[u]] >> 32 : 0ull;
+      const int32_t nh = in ? d.tk_info[i[u]] : 0;
+      lo[u] = max((int32_t)tl.ra, in ? d.tk_info[T + i[u]] : 0);
+      hi[u] = min((int32_t)tl.rb - 1, in ? d.tk_info[2 * T + i[u]] : -1);
+      const uint32_t pre = in ? d.own_part[(size_t)tt * T + i[u]] : 0u;
+      go[u] = in && co + (pk >> 32) <= d.max_track_clusters && lo[u] <= hi[u];   // capacity: flagged by finish()
+      key[u] = key32((uint32_t)nh, i[u]);
+      o[u] = (uint32_t)co + pre;
     }
+    int32_t h[kBatch][kTileRowsMax];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int rr = 0; rr < kTileRowsMax; ++rr) {
+        const int32_t r = (int32_t)tl.ra + rr;
+        h[u][rr] = (go[u] && r >= lo[u] && r <= hi[u]) ? d.tk_rowhit[(size_t)r * T + i[u]] : -1;
+      }
+    uint32_t id[kBatch][kTileRowsMax];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int rr = 0; rr < kTileRowsMax; ++rr) {
+        const bool own = h[u][rr] >= 0 && wt[(uint32_t)h[u][rr] - tl.first] == key[u];
+        if (!own) h[u][rr] = -1;
+        id[u][rr] = own ? d.sid[h[u][rr]] : 0u;
+      }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int rr = 0; rr < kTileRowsMax; ++rr)
+        if (h[u][rr] >= 0) d.out_clusters[o[u]++] = id[u][rr];
   }
 }
 
