@@ -12,25 +12,49 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// kBatch hits per thread at a time: each level of the dependent gathers
+// (own links, the linked hits' links, the next hit's links) is issued for the
+// whole batch before the next level needs it.
+constexpr int kBatch = 4;
+
 __global__ void __launch_bounds__(kThreads) k_clean(DevPtrs d) {
   __shared__ uint32_t wsum[kThreads / kWave];
   const uint32_t sr = blockIdx.x;
   const uint32_t a = d.row_off[sr], n = d.row_off[sr + 1] - a;
   uint32_t cnt = 0;
-  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
-    const int32_t h = (int32_t)(a + j);
-    const int32_t u = d.up0[h], dn = d.down0[h];
-    const int32_t u1 = (u >= 0 && d.down0[u] == h) ? u : -1;
-    const int32_t d1 = (dn >= 0 && d.up0[dn] == h) ? dn : -1;
-    d.up1[h] = u1;
-    d.down1[h] = d1;
-    bool start = false;
-    if (d1 == -1 && u1 >= 0) {
-      const int32_t uu = d.up0[u1];
-      start = uu >= 0 && d.down0[uu] == u1;   // up1[u1] >= 0
+  for (uint32_t j0 = threadIdx.x; j0 < n; j0 += kBatch * kThreads) {
+    int32_t u[kBatch], dn[kBatch], uback[kBatch], dback[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const uint32_t j = j0 + q * kThreads;
+      u[q] = j < n ? d.up0[a + j] : -1;
+      dn[q] = j < n ? d.down0[a + j] : -1;
     }
-    d.sflag[h] = start ? 1 : 0;
-    cnt += start;
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      uback[q] = u[q] >= 0 ? d.down0[u[q]] : -1;
+      dback[q] = dn[q] >= 0 ? d.up0[dn[q]] : -1;
+    }
+    int32_t u1[kBatch], d1[kBatch], uu[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int32_t h = (int32_t)(a + j0 + q * kThreads);
+      u1[q] = (u[q] >= 0 && uback[q] == h) ? u[q] : -1;
+      d1[q] = (dn[q] >= 0 && dback[q] == h) ? dn[q] : -1;
+      uu[q] = (d1[q] == -1 && u1[q] >= 0) ? d.up0[u1[q]] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const uint32_t j = j0 + q * kThreads;
+      const bool start = uu[q] >= 0 && d.down0[uu[q]] == u1[q];   // up1[u1] >= 0
+      if (j < n) {
+        const int32_t h = (int32_t)(a + j);
+        d.up1[h] = u1[q];
+        d.down1[h] = d1[q];
+        d.sflag[h] = start ? 1 : 0;
+        cnt += start;
+      }
+    }
   }
   uint32_t total;
   block_exclusive_scan<uint32_t>(cnt, wsum, &total);
