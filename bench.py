@@ -328,7 +328,7 @@ def main():
         "tracklets": dict(kernel=k5_name, bound="hbm", achieved=round(k5_gbs, 2), peak=HBM_PEAK_GBS,
                           unit="GB/s", frac=round(k5_gbs / HBM_PEAK_GBS, 5), traffic=pmc_traffic(wl["workload"], "tracklets"),
                           algorithmic_bytes=round(k5_bytes), kernel_ms=round(pass_ms["tracklets"], 4),
-                          note="latency-bound dependent row steps; bytes = 30 B/row step + 700 B/tracklet"),
+                          note="bound by instruction issue along dependent row steps, not bytes; bytes = 30 B/row step + 700 B/tracklet"),
         "grid": dict(kernel="k_grid_lds (K1, C1)", bound="hbm", achieved=round(k1_gbs, 2), peak=HBM_PEAK_GBS,
                      unit="GB/s", frac=round(k1_gbs / HBM_PEAK_GBS, 5), traffic=pmc_traffic(wl["workload"], "grid"),
                      algorithmic_bytes=round(K1_BYTES_PER_CLUSTER * N), kernel_ms=round(pass_ms["grid"], 4)),
