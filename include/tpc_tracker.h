@@ -261,9 +261,10 @@ tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule);
 
 /* Per-pass timing with HIP events on the tracker's stream, for later requests.
  * pass_mask: bit p times pass p (TPC_N_PASSES passes, in the order below);
- * 0 turns timing off, TPC_TIME_ALL_PASSES times every pass.  Each timed pass
- * costs up to two event records on the stream, so a caller that needs one
- * pass's time should time that pass alone. */
+ * 0 turns timing off, TPC_TIME_ALL_PASSES times every pass; TPC_E_INVAL for
+ * bits beyond the passes.  Each timed pass costs up to two event records on
+ * the stream, so a caller that needs one pass's time should time that pass
+ * alone. */
 #define TPC_N_PASSES 6     /* K1 grid, K2 neighbours, K3/K4 clean+starts, K5 tracklets, K6 select, output */
 #define TPC_TIME_ALL_PASSES 0x3F
 tpc_status tpc_set_timing(tpc_tracker* t, int32_t pass_mask);
