@@ -59,7 +59,10 @@ def lib():
         L.orc_run_create.restype = vp
         L.orc_run_create.argtypes = [C.POINTER(_Cfg), C.c_uint32, u32p, dp, dp, fp, fp]
         L.orc_run_destroy.argtypes = [vp]
-        for f in ("orc_run_grid", "orc_run_links", "orc_run_starts", "orc_run_select"):
+        i32p = C.POINTER(C.c_int32)
+        L.orc_run_from_tracklets.restype = vp
+        L.orc_run_from_tracklets.argtypes = [C.POINTER(_Cfg), C.c_uint32, C.c_uint64, i32p, u32p, i32p]
+        for f in ("orc_run_grid", "orc_run_links", "orc_run_links_fp64", "orc_run_starts", "orc_run_select"):
             getattr(L, f).argtypes = [vp]
             getattr(L, f).restype = C.c_int
         L.orc_run_construct.argtypes = [vp, u32p, C.c_uint64]
@@ -116,6 +119,20 @@ class Run:
                                       _ptr(self.z_lo, C.c_float), _ptr(self.z_hi, C.c_float))
 
     @classmethod
+    def from_tracklets(cls, cfg: dict, n_clusters, nhits, start_pos, rowhit):
+        """A run holding only given tracklets (rowhit [T, R] sorted positions, -1 none), for C6 alone."""
+        self = cls.__new__(cls)
+        self.cfg = Config(cfg)
+        self.R = self.cfg.s.n_rows
+        self._keep = (np.ascontiguousarray(nhits, np.int32), np.ascontiguousarray(start_pos, np.uint32),
+                      np.ascontiguousarray(rowhit, np.int32).reshape(-1))
+        T = len(self._keep[0])
+        assert len(self._keep[1]) == T and len(self._keep[2]) == T * self.R
+        self.h = lib().orc_run_from_tracklets(C.byref(self.cfg.s), n_clusters, T, _ptr(self._keep[0], C.c_int32),
+                                             _ptr(self._keep[1], C.c_uint32), _ptr(self._keep[2], C.c_int32))
+        return self
+
+    @classmethod
     def from_event(cls, cfg, ev, fp64=None):
         y = ev.y if fp64 is None else fp64[0]
         z = ev.z if fp64 is None else fp64[1]
@@ -137,8 +154,9 @@ class Run:
         lib().orc_run_grid(self.h)
         return self
 
-    def links(self):
-        lib().orc_run_links(self.h)
+    def links(self, fp64=False):
+        """C2 + C3; fp64=True evaluates the C2 decisions in double instead of float32."""
+        (lib().orc_run_links_fp64 if fp64 else lib().orc_run_links)(self.h)
         return self
 
     def starts(self):

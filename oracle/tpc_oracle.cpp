@@ -429,6 +429,25 @@ orc_run* orc_run_create(const orc_config* cfg, uint32_t n_sectors, const uint32_
 
 void orc_run_destroy(orc_run* r) { delete r; }
 
+// A run holding only given tracklets, for step C6 on its own: cluster ids
+// equal sorted positions, one sector.
+orc_run* orc_run_from_tracklets(const orc_config* cfg, uint32_t n_clusters, uint64_t n_tracklets, const int32_t* nhits,
+                                const uint32_t* start_pos, const int32_t* rowhit) {
+  orc_run* r = new orc_run();
+  r->cfg = *cfg;
+  r->S = 1;
+  r->R = (uint32_t)cfg->n_rows;
+  r->off.assign(r->R + 1, 0);
+  r->off[r->R] = n_clusters;
+  r->y = r->z = nullptr;
+  r->sorted_id.resize(n_clusters);
+  for (uint32_t i = 0; i < n_clusters; ++i) r->sorted_id[i] = i;
+  r->starts.assign(start_pos, start_pos + n_tracklets);
+  r->tk_nhits.assign(nhits, nhits + n_tracklets);
+  r->tk_rowhit.assign(rowhit, rowhit + n_tracklets * r->R);
+  return r;
+}
+
 // C1: per (sector, row) grid dimensions, bins and stable counting order.
 int orc_run_grid(orc_run* r) {
   const uint32_t SR = r->S * r->R, N = r->off[SR];
@@ -476,40 +495,75 @@ int orc_run_grid(orc_run* r) {
   return 0;
 }
 
-// C2 + C3.
-int orc_run_links(orc_run* r) {
+}  // extern "C"
+
+namespace {
+
+// C2 + C3.  The decisions of C2 are taken in float32 (as the definition
+// fixes them) unless fp64 is set: then windows, cut and deviation are
+// evaluated in double from the same coordinates, which shows how far the
+// float32 rule departs from an FP64 one (only at near-ties).
+int links_impl(orc_run* r, bool fp64) {
   const uint32_t SR = r->S * r->R, N = r->off[SR], R = r->R;
+  const orc_config& cfg = r->cfg;
   r->up0.assign(N, -1);
   r->down0.assign(N, -1);
   std::vector<uint32_t> U, D;
+  const double rho64 = (cfg.sigma_y / cfg.sigma_z) * (cfg.sigma_y / cfg.sigma_z);
   for (uint32_t sr = 0; sr < SR; ++sr) {
     const uint32_t row = sr % R;
     if (row == 0 || row + 1 >= R) continue;
     const RowC& c = r->rc[row];
+    // double-precision constants of the row (used when fp64)
+    const double du = cfg.row_x[row + 1] - cfg.row_x[row], dd = cfg.row_x[row] - cfg.row_x[row - 1];
+    const double t64 = dd / (dd + du);
+    const double wyu = cfg.win_a_y * du + cfg.win_b_y, wzu = cfg.win_a_z * du + cfg.win_b_z;
+    const double wyd = cfg.win_a_y * dd + cfg.win_b_y, wzd = cfg.win_a_z * dd + cfg.win_b_z;
+    const double dmax64 = (cfg.link_nsigma * cfg.link_nsigma * cfg.sigma_y * cfg.sigma_y) *
+                          ((1.0 + t64 * t64) + (1.0 - t64) * (1.0 - t64));
     for (uint32_t p = r->off[sr]; p < r->off[sr + 1]; ++p) {
       const float yh = r->fy[p], zh = r->fz[p];
+      const double yh64 = r->sy[p], zh64 = r->sz[p];
+      auto in_up = [&](uint32_t q) {
+        if (fp64) return std::fabs(r->sy[q] - yh64) <= wyu && std::fabs(r->sz[q] - zh64) <= wzu;
+        const float dy = r->fy[q] - yh, dz = r->fz[q] - zh;
+        return std::fabs(dy) <= c.wy_up && std::fabs(dz) <= c.wz_up;
+      };
+      auto in_dn = [&](uint32_t q) {
+        if (fp64) return std::fabs(r->sy[q] - yh64) <= wyd && std::fabs(r->sz[q] - zh64) <= wzd;
+        const float dy = r->fy[q] - yh, dz = r->fz[q] - zh;
+        return std::fabs(dy) <= c.wy_dn && std::fabs(dz) <= c.wz_dn;
+      };
       U.clear();
       D.clear();
       for_range(r, sr + 1, yh - (c.wy_up + kWinPad), yh + (c.wy_up + kWinPad), zh - (c.wz_up + kWinPad),
                 zh + (c.wz_up + kWinPad), [&](uint32_t q) {
-                  const float dy = r->fy[q] - yh, dz = r->fz[q] - zh;
-                  if (std::fabs(dy) <= c.wy_up && std::fabs(dz) <= c.wz_up) U.push_back(q);
+                  if (in_up(q)) U.push_back(q);
                 });
       if (U.empty()) continue;
       for_range(r, sr - 1, yh - (c.wy_dn + kWinPad), yh + (c.wy_dn + kWinPad), zh - (c.wz_dn + kWinPad),
                 zh + (c.wz_dn + kWinPad), [&](uint32_t q) {
-                  const float dy = r->fy[q] - yh, dz = r->fz[q] - zh;
-                  if (std::fabs(dy) <= c.wy_dn && std::fabs(dz) <= c.wz_dn) D.push_back(q);
+                  if (in_dn(q)) D.push_back(q);
                 });
       int32_t bu = -1, bd = -1;
-      float best = 0.0f;
+      double best = 0.0;
       for (uint32_t d : D)
         for (uint32_t u : U) {
-          const float yp = r->fy[d] + c.t * (r->fy[u] - r->fy[d]);
-          const float zp = r->fz[d] + c.t * (r->fz[u] - r->fz[d]);
-          const float ey = yh - yp, ez = zh - zp;
-          const float dev = ey * ey + r->rho * (ez * ez);
-          if (!(dev <= c.dmax)) continue;
+          double dev;
+          if (fp64) {
+            const double yp = r->sy[d] + t64 * (r->sy[u] - r->sy[d]);
+            const double zp = r->sz[d] + t64 * (r->sz[u] - r->sz[d]);
+            const double ey = yh64 - yp, ez = zh64 - zp;
+            dev = ey * ey + rho64 * (ez * ez);
+            if (!(dev <= dmax64)) continue;
+          } else {
+            const float yp = r->fy[d] + c.t * (r->fy[u] - r->fy[d]);
+            const float zp = r->fz[d] + c.t * (r->fz[u] - r->fz[d]);
+            const float ey = yh - yp, ez = zh - zp;
+            const float devf = ey * ey + r->rho * (ez * ez);
+            if (!(devf <= c.dmax)) continue;
+            dev = devf;
+          }
           if (bu < 0 || dev < best || (dev == best && ((int32_t)u < bu || ((int32_t)u == bu && (int32_t)d < bd)))) {
             best = dev;
             bu = (int32_t)u;
@@ -529,6 +583,13 @@ int orc_run_links(orc_run* r) {
   }
   return 0;
 }
+
+}  // namespace
+
+extern "C" {
+
+int orc_run_links(orc_run* r) { return links_impl(r, false); }
+int orc_run_links_fp64(orc_run* r) { return links_impl(r, true); }
 
 // C4: chain starts in ascending sorted position (= sector, row, grid order).
 int orc_run_starts(orc_run* r) {

@@ -53,8 +53,18 @@ orc_run* orc_run_create(const orc_config* cfg, uint32_t n_sectors, const uint32_
                         const float* sector_z_hi);
 void orc_run_destroy(orc_run* r);
 
+/* A run that holds only the given tracklets (T of them): nHits (<
+ * min_tracklet_hits = not valid), start positions, and rows ([T*n_rows],
+ * sorted positions, -1 = no hit), for step C6 on its own; cluster ids equal
+ * sorted positions.  Call orc_run_select on it. */
+orc_run* orc_run_from_tracklets(const orc_config* cfg, uint32_t n_clusters, uint64_t n_tracklets,
+                                const int32_t* nhits, const uint32_t* start_pos, const int32_t* rowhit);
+
 int orc_run_grid(orc_run* r);                 /* C1 */
 int orc_run_links(orc_run* r);                /* C2 + C3 */
+/* C2 + C3 with the C2 windows, cut and deviation evaluated in double instead
+ * of the float32 the definition fixes (to show where the two differ). */
+int orc_run_links_fp64(orc_run* r);
 int orc_run_starts(orc_run* r);               /* C4 */
 /* C5 on the listed start indices (NULL = all starts). */
 int orc_run_construct(orc_run* r, const uint32_t* which, uint64_t n_which);
