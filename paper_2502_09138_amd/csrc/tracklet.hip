@@ -1,10 +1,11 @@
 // K5: tracklet constructor -- step C5 of the tracker definition.
 //
 // One lane per tracklet (chain start).  The helix state p[5] and packed
-// covariance C[15] live in float32 registers; the transport exploits the
-// sparsity of the Jacobian (6 non-trivial entries) and the update uses the
-// Joseph form, which keeps the float32 covariance positive definite on short,
-// strongly curved fits where the plain C - KHC form does not.  The lane walks
+// covariance C[15] are accumulated in double registers (see par_t / cov_t);
+// the per-step increments and the Jacobian are float32.  The transport
+// exploits the sparsity of the Jacobian (6 non-trivial entries) and the update
+// uses the Joseph form, which keeps the covariance positive definite on
+// short, strongly curved fits.  The lane walks
 // its chain (dependent up1 gathers), seeds from three chain hits, fits the
 // chain, extends outward through the row grids and refits inward with a fresh
 // covariance, filling gaps and extending below the chain.
@@ -12,8 +13,9 @@
 // Latency is the bound (each row step is a dependent chain: propagate ->
 // grid lookup -> candidate loads -> update), so the per-row constants are
 // staged in LDS, a row's grid is located with one 8-byte load, and the
-// Kalman arithmetic uses the hardware reciprocal / square root (the step is
-// tolerance-checked against the FP64 definition, not bit-exact).
+// float32 step arithmetic uses the hardware reciprocal / square root (its
+// rounding is relative to one row step; the results are checked against the
+// FP64 definition to 1e-4 relative, not bit-exact).
 //
 // The per-tracklet row -> hit column lives in global memory (row-major over
 // tracklets, so lanes at the same row write one coalesced segment); the
@@ -38,14 +40,48 @@ constexpr int kPair = 2;
 constexpr int kTrkPerWave = kThreads / kPair;
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }   // i >= j
+
+// Arithmetic types of the Kalman state p and of its covariance C.  Both are
+// accumulated in double: a track's covariance shrinks by up to seven orders
+// of magnitude under strongly correlated updates (y, sin phi and q/pT move
+// together), so a float32 recursion loses about 1e-2 of its relative
+// precision, and a float32 state rounds every row's increment of sin phi and
+// y into values hundreds of times larger, which shifts the fitted q/pT by
+// more than 1e-4.  Everything evaluated per row step from the state (the
+// increments, the Jacobian, the search window) stays in float32, where its
+// rounding is relative to the step itself.
+using par_t = double;
+using cov_t = double;
+
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float frsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fabs_(float x) { return fabsf(x); }
+// double reciprocal: the float32 hardware estimate refined by one Newton step (relative error ~1e-14)
+__device__ __forceinline__ double frcp(double x) {
+  const double r = __builtin_amdgcn_rcpf(float(x));
+  return r * (2.0 - x * r);
+}
+__device__ __forceinline__ double fabs_(double x) { return fabs(x); }
 
 struct Trk {
+  par_t p[5];
+  cov_t c[15];
+};
+
+// The state at the innermost hit of the inward pass, in the float32 the result is stored in.
+struct Snap {
   float p[5];
   float c[15];
 };
+__device__ __forceinline__ Snap snap_of(const Trk& t) {
+  Snap s;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) s.p[q] = float(t.p[q]);
+#pragma unroll
+  for (int q = 0; q < 15; ++q) s.c[q] = float(t.c[q]);
+  return s;
+}
 
 // Per-row constants used in the tracklet loop: x, half-width, y_lo, 1/(2Y).
 struct RowK {
@@ -64,17 +100,23 @@ __device__ __forceinline__ float asin_over_prime(float u) {
     return u * (1.0f / 3.0f + u2 * (3.0f / 10.0f + u2 * (15.0f / 56.0f + u2 * (35.0f / 144.0f))));
   return (u * frsqrt(1.0f - u2) - asinf(u)) / u2;
 }
-
 // Helix transport from x to x + dx with covariance; false on |sin phi| >= s_max or |u| >= 1.
 // kNoExit: the failure tests do not branch (the row-synchronous waves, where a
 // branch costs every lane); on false the state then holds meaningless values,
 // and every caller stops the tracklet without reading it again.
+//
+// The increments of one row step (dy, dz, kappa*dx) and the Jacobian are
+// evaluated in float32: their rounding is relative to the step, far below the
+// tolerance.  They are accumulated into the state in par_t, and the covariance
+// is transported in cov_t.
 template <bool kNoExit>
 __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
-  const float s1 = t.p[2], tl = t.p[3], qp = t.p[4];
+  using V = cov_t;
+  const float s1 = float(t.p[2]), tl = float(t.p[3]), qp = float(t.p[4]);
   const float kap = k.bk * qp;
+  const par_t s2p = t.p[2] + par_t(kap * dx);
+  const float s2 = float(s2p);
   if (!kNoExit && !(fabsf(s1) < k.s_max)) return false;
-  const float s2 = s1 + kap * dx;
   if (!kNoExit && !(fabsf(s2) < k.s_max)) return false;
   const float c1 = fsqrt((1.0f - s1) * (1.0f + s1));
   const float c2 = fsqrt((1.0f - s2) * (1.0f + s2));
@@ -94,23 +136,23 @@ __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
   const float dS_dL = sgn * frsqrt(1.0f - u * u);
   const float dS_dkap = sgn * 0.5f * L * L * asin_over_prime(u);
   const float dL_ddy = L > 0.0f ? dy * frcp(L) : 0.0f;
-  const float A = ddy_ds1;                                // F02
-  const float B = ddy_dk;                                 // F04
-  const float Cc = tl * dS_dL * dL_ddy * ddy_ds1;         // F12
-  const float Dd = S;                                     // F13
-  const float E = tl * (dS_dL * dL_ddy * ddy_dk + dS_dkap * k.bk);  // F14
-  const float Fk = k.bk * dx;                             // F24
-  t.p[0] += dy;
-  t.p[1] += tl * S;
-  t.p[2] = s2;
+  const V A = ddy_ds1;                                  // F02
+  const V B = ddy_dk;                                   // F04
+  const V Cc = tl * dS_dL * dL_ddy * ddy_ds1;           // F12
+  const V Dd = S;                                       // F13
+  const V E = tl * (dS_dL * dL_ddy * ddy_dk + dS_dkap * k.bk);  // F14
+  const V Fk = k.bk * dx;                               // F24
+  t.p[0] += par_t(dy);
+  t.p[1] += par_t(tl * S);
+  t.p[2] = s2p;
   // C' = F C F^T with F = I + {02:A, 04:B, 12:Cc, 13:Dd, 14:E, 24:Fk}
-  float* c = t.c;
-  float M[5][5];
+  V* c = t.c;
+  V M[5][5];
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
     for (int j = 0; j < 5; ++j) M[i][j] = i >= j ? c[tri(i, j)] : c[tri(j, i)];
-  float G[5][5];   // G = F C
+  V G[5][5];   // G = F C
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
     G[0][j] = M[0][j] + A * M[2][j] + B * M[4][j];
@@ -121,11 +163,11 @@ __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) {   // C'_ij = sum_k G_ik F_jk
-    const float g0 = G[i][0], g1 = G[i][1], g2 = G[i][2], g3 = G[i][3], g4 = G[i][4];
-    const float r0 = g0 + A * g2 + B * g4;
-    const float r1 = g1 + Cc * g2 + Dd * g3 + E * g4;
-    const float r2 = g2 + Fk * g4;
-    const float rr[5] = {r0, r1, r2, g3, g4};
+    const V g0 = G[i][0], g1 = G[i][1], g2 = G[i][2], g3 = G[i][3], g4 = G[i][4];
+    const V r0 = g0 + A * g2 + B * g4;
+    const V r1 = g1 + Cc * g2 + Dd * g3 + E * g4;
+    const V r2 = g2 + Fk * g4;
+    const V rr[5] = {r0, r1, r2, g3, g4};
 #pragma unroll
     for (int j = 0; j <= i; ++j) c[tri(i, j)] = rr[j];
   }
@@ -134,50 +176,53 @@ __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
 
 // Kalman update with a measurement of (y, z), Joseph form.
 __device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst& k, float& chi2) {
-  float* c = t.c;
-  const float r0 = ym - t.p[0], r1 = zm - t.p[1];
-  const float S00 = c[0] + k.vy, S01 = c[1], S11 = c[2] + k.vz;
-  const float id = frcp(S00 * S11 - S01 * S01);
-  const float I00 = S11 * id, I01 = -S01 * id, I11 = S00 * id;
-  float c0[5], c1[5];   // columns 0 and 1 of C (C_i0, C_i1)
+  using P = par_t;
+  using V = cov_t;
+  V* c = t.c;
+  const V vy = k.vy, vz = k.vz;
+  const V r0 = V(P(ym) - t.p[0]), r1 = V(P(zm) - t.p[1]);
+  const V S00 = c[0] + vy, S01 = c[1], S11 = c[2] + vz;
+  const V id = frcp(S00 * S11 - S01 * S01);
+  const V I00 = S11 * id, I01 = -S01 * id, I11 = S00 * id;
+  V c0[5], c1[5];   // columns 0 and 1 of C (C_i0, C_i1)
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     c0[i] = c[tri(i, 0)];
     c1[i] = i >= 1 ? c[tri(i, 1)] : c[tri(1, 0)];
   }
-  float K0[5], K1[5];
+  V K0[5], K1[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     K0[i] = c0[i] * I00 + c1[i] * I01;
     K1[i] = c0[i] * I01 + c1[i] * I11;
-    t.p[i] += K0[i] * r0 + K1[i] * r1;
+    t.p[i] += P(K0[i] * r0 + K1[i] * r1);
   }
   // P = (I - K H) C, then C' = P (I - K H)^T + K V K^T on the lower triangle,
   // grouped as C' = P + D K^T with D = K V - P H^T (columns 0 and 1 of P)
-  float P[5][5];
+  V Pm[5][5];
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-      const float cij = i >= j ? c[tri(i, j)] : c[tri(j, i)];
-      P[i][j] = cij - K0[i] * c0[j] - K1[i] * c1[j];
+      const V cij = i >= j ? c[tri(i, j)] : c[tri(j, i)];
+      Pm[i][j] = cij - K0[i] * c0[j] - K1[i] * c1[j];
     }
-  float D0[5], D1[5];
+  V D0[5], D1[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    D0[i] = K0[i] * k.vy - P[i][0];
-    D1[i] = K1[i] * k.vz - P[i][1];
+    D0[i] = K0[i] * vy - Pm[i][0];
+    D1[i] = K1[i] * vz - Pm[i][1];
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j) c[tri(i, j)] = P[i][j] + D0[i] * K0[j] + D1[i] * K1[j];
-  chi2 += r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);
+    for (int j = 0; j <= i; ++j) c[tri(i, j)] = Pm[i][j] + D0[i] * K0[j] + D1[i] * K1[j];
+  chi2 += float(r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1));
 }
 
 __device__ __forceinline__ void set_c0(Trk& t, const KfConst& k) {
 #pragma unroll
-  for (int i = 0; i < 15; ++i) t.c[i] = 0.0f;
+  for (int i = 0; i < 15; ++i) t.c[i] = cov_t(0);
   t.c[tri(0, 0)] = k.vy;
   t.c[tri(1, 1)] = k.vz;
   t.c[tri(2, 2)] = k.c0_sinphi;
@@ -194,10 +239,10 @@ constexpr int kGroupLds = 4;   // the same for the LDS search
 
 __device__ __forceinline__ int32_t search_m(const DevPtrs& d, uint2 meta, const RowK& rk, const SectorConst& sc,
                                             const Trk& t, const KfConst& k, float zref, float2& hv) {
-  const float sy2 = t.c[0] + k.vy, sz2 = t.c[2] + k.vz;
+  const float sy2 = float(t.c[0] + cov_t(k.vy)), sz2 = float(t.c[2] + cov_t(k.vz));
   const float wy = fminf(k.gate * fsqrt(sy2), k.cap), wz = fminf(k.gate * fsqrt(sz2), k.cap);
   const float isy = frcp(sy2), isz = frcp(sz2);
-  const float yp = t.p[0], zp = t.p[1];          // zp relative to zref
+  const float yp = float(t.p[0]), zp = float(t.p[1]);          // zp relative to zref
   const float za = zref + zp;                     // absolute, for the bin range only
   const int ny = (int)(meta.y & 0xFFFFu), nz = (int)(meta.y >> 16);
   const int iy0 = bin1((yp - wy) - kWinPad, rk.y_lo, rk.inv_wy, ny);
@@ -256,10 +301,10 @@ __device__ __forceinline__ int pair_swap(int v) {   // value of the other lane o
 __device__ __forceinline__ int32_t search_lds(const float2* yz, const uint32_t* bs, uint32_t first, uint2 meta,
                                               const RowK& rk, const SectorConst& sc, const Trk& t, const KfConst& k,
                                               float zref, uint32_t half) {
-  const float sy2 = t.c[0] + k.vy, sz2 = t.c[2] + k.vz;
+  const float sy2 = float(t.c[0] + cov_t(k.vy)), sz2 = float(t.c[2] + cov_t(k.vz));
   const float wy = fminf(k.gate * fsqrt(sy2), k.cap), wz = fminf(k.gate * fsqrt(sz2), k.cap);
   const float isy = frcp(sy2), isz = frcp(sz2);
-  const float yp = t.p[0], zp = t.p[1];
+  const float yp = float(t.p[0]), zp = float(t.p[1]);
   const float za = zref + zp;
   const int ny = (int)(meta.y & 0xFFFFu), nz = (int)(meta.y >> 16);
   const int iy0 = bin1((yp - wy) - kWinPad, rk.y_lo, rk.inv_wy, ny);
@@ -384,7 +429,7 @@ __device__ __forceinline__ void spd_guard(float* c) {
 }
 
 __device__ __forceinline__ void store_tracklet(const DevPtrs& d, uint32_t i, int nh, uint32_t rin, uint32_t rout,
-                                               uint32_t r0, const Trk& snap, float chi2, float zref) {
+                                               uint32_t r0, const Snap& snap, float chi2, float zref) {
   const uint32_t T = d.tcap;
   d.tk_info[i] = nh;
   d.tk_info[T + i] = (int32_t)rin;
@@ -462,7 +507,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
     }
     uint32_t steps = n - 1;
     // upward extension
-    float pout[5];
+    par_t pout[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
     uint32_t rout = rl;
@@ -475,7 +520,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
       ++steps;
       if (!propagate<false>(t, rk.x - xprev, k)) break;
       xprev = rk.x;
-      if (fabsf(t.p[0]) > rk.half_y + k.margin) break;
+      if (fabs_(t.p[0]) > rk.half_y + k.margin) break;
       float2 hm = make_float2(0.0f, 0.0f);
       const int32_t h = search_m(d, meta, rk, sc, t, k, zref, hm);
       H[(size_t)r * T] = h;
@@ -500,7 +545,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
     set_c0(t, k);
     chi2 = 0.0f;
     int nh = 1;
-    Trk snap = t;
+    Snap snap = snap_of(t);
     uint32_t rin = rout;
     xprev = lrows[rout].x;
     miss = 0;
@@ -523,7 +568,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
       if (!propagate<false>(t, rk.x - xprev, k)) break;
       xprev = rk.x;
       const bool below = (uint32_t)r < r0;
-      if (below && fabsf(t.p[0]) > rk.half_y + k.margin) break;
+      if (below && fabs_(t.p[0]) > rk.half_y + k.margin) break;
       int32_t h = hk;
       float2 hm = vk;
       if (h < 0) {
@@ -533,7 +578,7 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
       if (h >= 0) {
         update(t, hm.x, hm.y - zref, k, chi2);
         ++nh;
-        snap = t;
+        snap = snap_of(t);
         rin = (uint32_t)r;
         if (below) miss = 0;
       } else if (below && ++miss > k.max_miss) {
@@ -668,7 +713,9 @@ __device__ __forceinline__ void commit_row(const Prefetch& pf, f32x4* yz4_s, u32
 }
 
 // Three waves per SIMD (<= 168 VGPRs) keep every wave of a central event
-// resident at once.
+// resident at once.  The double-precision state then spills about 40 VGPRs
+// to scratch; measured on a central event this is faster than two waves per
+// SIMD without spills (0.86 against 1.09 ms).
 template <bool kAllFit>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) k_tracklets_rs(DevPtrs d, KfConst k) {
   __shared__ RowK lrows[kMaxRows];
@@ -741,7 +788,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
     uint32_t steps = ok ? n - 1 : 0;
     // ---- outward sweep ----
     bool up = ok, failed = false;
-    float pout[5];
+    par_t pout[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
     uint32_t rout = rl;
@@ -775,7 +822,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
         const bool pok = propagate<true>(t, rk.x - xprev, k);
         xprev = rk.x;
         failed = failed || (!pok && chain);
-        const bool go = pok && (chain || fabsf(t.p[0]) <= rk.half_y + k.margin);
+        const bool go = pok && (chain || fabs_(t.p[0]) <= rk.half_y + k.margin);
         up = go;
         int32_t h = hchain;
         if (go && !chain) {
@@ -810,7 +857,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
     // ---- inward sweep from each lane's outermost hit, fresh covariance ----
     bool down = ok;
     int nh = 1;
-    Trk snap;
+    Snap snap;
     uint32_t rin = rout;
     if (down) {
       const float2 ho = d.syz[H[(size_t)rout * T]];
@@ -820,7 +867,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
       t.p[1] = ho.y - zref;
       set_c0(t, k);
       chi2 = 0.0f;
-      snap = t;
+      snap = snap_of(t);
       xprev = lrows[rout].x;
       miss = 0;
     }
@@ -843,7 +890,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
         const bool pok = propagate<true>(t, rk.x - xprev, k);
         xprev = rk.x;
         const bool below = (uint32_t)rr < r0;
-        const bool go = pok && !(below && fabsf(t.p[0]) > rk.half_y + k.margin);
+        const bool go = pok && !(below && fabs_(t.p[0]) > rk.half_y + k.margin);
         down = go;
         int32_t h = below ? -1 : hrow;
         if (go && h < 0) {
@@ -856,7 +903,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
           const float2 hm = (kAllFit || st.fits) ? yz_s[(uint32_t)h - st.first] : d.syz[h];
           update(t, hm.x, hm.y - zref, k, chi2);
           ++nh;
-          snap = t;
+          snap = snap_of(t);
           rin = (uint32_t)rr;
           if (below) miss = 0;
         }

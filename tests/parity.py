@@ -2,29 +2,18 @@
 
 Tolerances (stated in the tests that use them):
 * C1-C4 (grid order, bin starts, dims, links, starts): bit-exact.
-* C5/C6 (FP32 Kalman filter on the GPU vs FP64 oracle):
+* C5/C6 (the GPU's Kalman filter against the FP64 oracle):
   - assignment agreement >= 99.9% over clusters labelled by either side
     (label = start position of the owning track);
-  - parameters of tracks found by both sides with the same clusters:
-    >= 98% within |dp_i| <= 1e-4 * max(|p_i|, f_i), f = (1 cm, 1 cm, 1e-2,
-    1e-2, 1e-2 /GeV); >= 99.5% within that bound or 0.5 sigma_i, and every
-    track within that bound or 2 sigma_i (sigma from the oracle covariance);
-  - covariance diagonal: >= 98% within 1e-2 relative, all within 0.1;
+  - parameters of every track (and tracklet) found by both sides with the same
+    clusters within |dp_i| <= 1e-4 * max(|p_i|, f_i), f = (1 cm, 1 cm, 1e-2,
+    1e-2, 1e-2 /GeV): the 1e-4 relative tolerance on track parameters, with
+    floors for parameters that cross zero;
+  - covariance diagonal of every such track within 1e-3 relative;
   - every GPU covariance SPD.
-  Where these come from: the inward refit is an extended Kalman filter whose
-  linearisation points (sin phi, tan lambda, q/pT handed over from the outward
-  pass) carry the outward pass's float32 rounding.  Strongly curved short fits
-  (pT < 0.2 GeV, <= 30 hits, |sin phi| > 0.7) turn that into gain differences
-  of up to a few percent.  Over 2630 central-event tracks the float32 path
-  differs from FP64 by: covariance p50 8e-6, p99 1.1e-2, max 5.9e-2 relative;
-  parameters p50 0.01, p99 1.14 times the 1e-4 bound.  Running the update or
-  the covariance transport alone in double does not change these figures, so
-  they are not the rounding of one step.  Two kinds of track sit beyond the
-  relative bound by more: stiff tracks, whose q/pT rests on sin(phi)
-  increments of ~1e-5 per row (one float32 ulp of sin(phi) is ~6e-8, so
-  |dq/pT| ~ 3e-5 /GeV = 1e-4 sigma), and the rare fake looper fitted beyond
-  the seeding range (|q/pT| > 10 /GeV, |sin phi| ~ 0.9), where the two
-  precisions can part by up to ~1.5 sigma.
+  The GPU accumulates the state and the covariance in double and evaluates
+  each row step's increments in float32; the float32 rounding is then relative
+  to one step's increment and the results sit far inside these bounds.
 """
 from __future__ import annotations
 
@@ -33,12 +22,8 @@ import numpy as np
 FLOORS = np.array([1.0, 1.0, 1e-2, 1e-2, 1e-2])
 PARAM_RTOL = 1e-4
 PARAM_SIGMA_CAP = 0.5
-PARAM_SIGMA_MAX = 2.0
-MIN_FRAC_SIGMA = 0.995
-COV_RTOL = 1e-2
-COV_RTOL_MAX = 0.1
+COV_RTOL = 1e-3
 MIN_AGREEMENT = 0.999
-MIN_FRAC_WITHIN = 0.98
 
 
 def gpu_run(tr, ev, dbg=True, tracklets=True):
@@ -100,7 +85,7 @@ def tracklet_stats(g, o, R, base=0, sample=None):
     same_hits = 0
     n_cmp = 0
     worst = 0.0
-    bad_param = far_param = very_far = 0
+    bad_param = far_param = 0
     for i_o in which:
         nh_o = int(o["tk_nhits"][i_o])
         if nh_o == 0:
@@ -126,9 +111,8 @@ def tracklet_stats(g, o, R, base=0, sample=None):
         bad_param += int(r > 1.0)
         sd = np.sqrt(np.diag(unpack_cov(o["tk_cov"][i_o])))
         far_param += int(r > 1.0 and np.any(dp > PARAM_SIGMA_CAP * sd))
-        very_far += int(r > 1.0 and np.any(dp > PARAM_SIGMA_MAX * sd))
     return dict(n=n_cmp, same_hits=same_hits, frac_same=same_hits / max(1, n_cmp), worst_param_ratio=float(worst),
-                bad_param=bad_param, far_param=far_param, very_far_param=very_far)
+                bad_param=bad_param, far_param=far_param)
 
 
 def labels_gpu(tracks, n_total, base=0, n=None):
@@ -169,7 +153,7 @@ def compare_tracks(tracks, o, n_total, base=0):
     o_by_start = {}
     for t, i in enumerate(o["trk_tracklet"]):
         o_by_start[int(st_o[i])] = (t, int(i))
-    n_both = n_same = bad_p = bad_c = far_p = far_c = vfar_p = 0
+    n_both = n_same = bad_p = bad_c = far_p = 0
     worst = 0.0
     worst_c = 0.0
     n_spd_fail = 0
@@ -197,13 +181,27 @@ def compare_tracks(tracks, o, n_total, base=0):
         bad_p += int(r > 1.0)
         do = np.diag(unpack_cov(o["tk_cov"][io]))
         far_p += int(r > 1.0 and np.any(dp > PARAM_SIGMA_CAP * np.sqrt(do)))
-        vfar_p += int(r > 1.0 and np.any(dp > PARAM_SIGMA_MAX * np.sqrt(do)))
         dg = np.diag(unpack_cov(tracks.cov[t].astype(np.float64)))
         rc = np.max(np.abs(dg - do) / np.abs(do))
         worst_c = max(worst_c, rc)
         bad_c += int(rc > COV_RTOL)
-        far_c += int(rc > COV_RTOL_MAX)
     return dict(agreement=agree, n_labelled=int(either.sum()), n_tracks_gpu=int(tracks.n_tracks),
                 n_tracks_oracle=len(o["trk_tracklet"]), n_both=n_both, n_same=n_same, bad_param=bad_p,
-                far_param=far_p, very_far_param=vfar_p, worst_param_ratio=float(worst), bad_cov=bad_c, far_cov=far_c,
+                far_param=far_p, worst_param_ratio=float(worst), bad_cov=bad_c,
                 worst_cov_rel=float(worst_c), spd_fail=n_spd_fail)
+
+
+def check_tracks(st):
+    """The track-level bars (module docstring)."""
+    assert st["agreement"] >= MIN_AGREEMENT, st
+    assert st["spd_fail"] == 0, st
+    assert st["n_same"] >= 0.98 * st["n_both"], st
+    assert st["bad_param"] == 0, st
+    assert st["bad_cov"] == 0, st
+
+
+def check_tracklets(ts):
+    """The tracklet-level bars: >= 98% of tracklets with the same hits on both
+    sides, and every one of those within the parameter tolerance."""
+    assert ts["frac_same"] >= 0.98, ts
+    assert ts["bad_param"] == 0, ts
