@@ -177,6 +177,24 @@ uint64_t tpc_workspace_bytes(const tpc_tracker_config* cfg);
 tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out);
 void tpc_tracker_destroy(tpc_tracker* t);
 
+/* Per-request workspaces (a server carving workspaces out of one budgeted
+ * pool).  tpc_workspace_bytes_for: device bytes a binding for at most
+ * max_clusters / max_sectors needs on tracker t (tracklet, track and track-
+ * cluster capacities follow the defaults for max_clusters, limited by t's
+ * create-time ones); 0 if the capacities exceed those t was created with.
+ * tpc_tracker_bind_workspace: moves t onto caller-owned device memory of
+ * workspace_bytes (>= tpc_workspace_bytes_for, 256-byte aligned) with those
+ * capacities; later requests are limited to them.  Allowed only between
+ * requests (TPC_E_BUSY while one is in flight); a workspace the tracker had
+ * allocated itself is freed.  The caller keeps the memory alive, and does
+ * not reuse it, until the next bind, a release of the last request on it,
+ * or destroy.  Costs one small host-to-device copy on the tracker's stream
+ * (the row constants).  TPC_E_INVAL for a NULL or misaligned workspace, too
+ * few bytes, or capacities beyond the create-time ones. */
+uint64_t tpc_workspace_bytes_for(const tpc_tracker* t, uint64_t max_clusters, uint32_t max_sectors);
+tpc_status tpc_tracker_bind_workspace(tpc_tracker* t, void* workspace, uint64_t workspace_bytes,
+                                      uint64_t max_clusters, uint32_t max_sectors);
+
 enum { TPC_IN_DEVICE = 0u, TPC_IN_HOST = 1u };
 
 typedef struct {
@@ -197,6 +215,7 @@ typedef struct {
  * once.  Errors in the host-side validation return TPC_E_INVAL and enqueue
  * nothing. */
 tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* tf, uint64_t* request_id);
+
 
 typedef struct {
   uint32_t n_tracks;

@@ -155,8 +155,13 @@ std::string validate_config(const tpc_tracker_config* c) {
 struct tpc_tracker {
   tpc_tracker_config cfg{};
   std::vector<double> row_x, row_half_y;
-  Caps caps{};
+  Caps caps{};        // capacities of the current workspace binding
   Layout lay{};
+  Caps host_caps{};   // capacities the pinned host buffers are sized for (create time)
+  // the workspace requests run on (create or bind_workspace)
+  char* home_ws = nullptr;
+  Caps home_caps{};
+  Layout home_lay{};
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -166,6 +171,7 @@ struct tpc_tracker {
   KfConst kc{};
   std::vector<RowConst> rows;
   // pinned host memory
+  RowConst* h_rows = nullptr;   // row constants, uploaded into each workspace binding
   char* h_frame = nullptr;   // pinned mirror of the row_off / tile_off / secs block
   uint32_t* h_row_off = nullptr;
   uint32_t* h_tile_off = nullptr;
@@ -183,6 +189,75 @@ struct tpc_tracker {
   uint32_t cur_S = 0, cur_N = 0;
   tpc_tracks out{};
 };
+
+namespace {
+
+// Device pointers of every workspace buffer for the current binding (t->ws,
+// t->lay, t->caps), and the pinned mirror's views of the per-frame block.
+void carve(tpc_tracker* t) {
+  DevPtrs& d = t->d;
+  char* w = t->ws;
+  const Layout& lay = t->lay;
+  const Caps& caps = t->caps;
+  const tpc_tracker_config* cfg = &t->cfg;
+  const KfConst& k = t->kc;
+  const uint32_t R = caps.R;
+  d.row_off = (const uint32_t*)(w + lay.row_off);
+  d.rows = (const RowConst*)(w + lay.rows);
+  d.secs = (const SectorConst*)(w + lay.secs);
+  d.row_dims = (uint32_t*)(w + lay.row_dims);
+  d.row_meta = (uint2*)(w + lay.row_meta);
+  d.bin_start = (uint32_t*)(w + lay.bin_start);
+  d.syz = (float2*)(w + lay.syz);
+  d.sid = (uint32_t*)(w + lay.sid);
+  d.up0 = (int32_t*)(w + lay.up0);
+  d.down0 = (int32_t*)(w + lay.down0);
+  d.up1 = (int32_t*)(w + lay.up1);
+  d.down1 = (int32_t*)(w + lay.down1);
+  d.sflag = (uint8_t*)(w + lay.sflag);
+  d.row_nstart = (uint32_t*)(w + lay.row_nstart);
+  d.row_start_off = (uint32_t*)(w + lay.row_start_off);
+  d.start_pos = (uint32_t*)(w + lay.start_pos);
+  d.start_sr = (uint32_t*)(w + lay.start_sr);
+  d.wave_off = (uint32_t*)(w + lay.wave_off);
+  d.tile_off = (const uint32_t*)(w + lay.tile_off);
+  d.tile_sr = (uint32_t*)(w + lay.tile_sr);
+  d.tk_rowhit = (int32_t*)(w + lay.tk_rowhit);
+  d.tk_info = (int32_t*)(w + lay.tk_info);
+  d.tk_param = (float*)(w + lay.tk_param);
+  d.tk_cov = (float*)(w + lay.tk_cov);
+  d.tk_chi2 = (float*)(w + lay.tk_chi2);
+  d.W = (uint32_t*)(w + lay.W);
+  d.own_part = (uint8_t*)(w + lay.own_part);
+  d.tk_pack = (unsigned long long*)(w + lay.tk_pack);
+  d.tk_scan = (unsigned long long*)(w + lay.tk_scan);
+  d.acc_list = (uint32_t*)(w + lay.acc_list);
+  d.out_sector = (uint32_t*)(w + lay.out_sector);
+  d.out_start = (uint32_t*)(w + lay.out_start);
+  d.out_first = (uint32_t*)(w + lay.out_first);
+  d.out_clusters = (uint32_t*)(w + lay.out_clusters);
+  d.out_xref = (float*)(w + lay.out_xref);
+  d.out_param = (float*)(w + lay.out_param);
+  d.out_cov = (float*)(w + lay.out_cov);
+  d.out_chi2 = (float*)(w + lay.out_chi2);
+  d.out_ndf = (int32_t*)(w + lay.out_ndf);
+  d.scan_blocks = (unsigned long long*)(w + lay.scan_blocks);
+  d.hdr = (ResultHeader*)(w + lay.hdr);
+  d.grid_k = cfg->grid_hits_per_bin;
+  d.k5_mode = cfg->tracklet_schedule;
+  d.rho = k.rho;
+  d.R = R;
+  d.tcap = (uint32_t)caps.T;
+  d.max_tracks = (uint32_t)caps.MT;
+  d.max_track_clusters = caps.MC;
+  if (t->h_frame) {
+    t->h_row_off = (uint32_t*)t->h_frame;
+    t->h_tile_off = (uint32_t*)(t->h_frame + (lay.tile_off - lay.row_off));
+    t->h_secs = (SectorConst*)(t->h_frame + (lay.secs - lay.row_off));
+  }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -307,68 +382,21 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   k.min_track_hits = cfg->min_track_hits;
   k.grid_k = cfg->grid_hits_per_bin;
   k.n_rows = cfg->n_rows;
-  // device pointers
-  DevPtrs& d = t->d;
-  char* w = t->ws;
-  d.row_off = (const uint32_t*)(w + lay.row_off);
-  d.rows = (const RowConst*)(w + lay.rows);
-  d.secs = (const SectorConst*)(w + lay.secs);
-  d.row_dims = (uint32_t*)(w + lay.row_dims);
-  d.row_meta = (uint2*)(w + lay.row_meta);
-  d.bin_start = (uint32_t*)(w + lay.bin_start);
-  d.syz = (float2*)(w + lay.syz);
-  d.sid = (uint32_t*)(w + lay.sid);
-  d.up0 = (int32_t*)(w + lay.up0);
-  d.down0 = (int32_t*)(w + lay.down0);
-  d.up1 = (int32_t*)(w + lay.up1);
-  d.down1 = (int32_t*)(w + lay.down1);
-  d.sflag = (uint8_t*)(w + lay.sflag);
-  d.row_nstart = (uint32_t*)(w + lay.row_nstart);
-  d.row_start_off = (uint32_t*)(w + lay.row_start_off);
-  d.start_pos = (uint32_t*)(w + lay.start_pos);
-  d.start_sr = (uint32_t*)(w + lay.start_sr);
-  d.wave_off = (uint32_t*)(w + lay.wave_off);
-  d.tile_off = (const uint32_t*)(w + lay.tile_off);
-  d.tile_sr = (uint32_t*)(w + lay.tile_sr);
-  d.tk_rowhit = (int32_t*)(w + lay.tk_rowhit);
-  d.tk_info = (int32_t*)(w + lay.tk_info);
-  d.tk_param = (float*)(w + lay.tk_param);
-  d.tk_cov = (float*)(w + lay.tk_cov);
-  d.tk_chi2 = (float*)(w + lay.tk_chi2);
-  d.W = (uint32_t*)(w + lay.W);
-  d.own_part = (uint8_t*)(w + lay.own_part);
-  d.tk_pack = (unsigned long long*)(w + lay.tk_pack);
-  d.tk_scan = (unsigned long long*)(w + lay.tk_scan);
-  d.acc_list = (uint32_t*)(w + lay.acc_list);
-  d.out_sector = (uint32_t*)(w + lay.out_sector);
-  d.out_start = (uint32_t*)(w + lay.out_start);
-  d.out_first = (uint32_t*)(w + lay.out_first);
-  d.out_clusters = (uint32_t*)(w + lay.out_clusters);
-  d.out_xref = (float*)(w + lay.out_xref);
-  d.out_param = (float*)(w + lay.out_param);
-  d.out_cov = (float*)(w + lay.out_cov);
-  d.out_chi2 = (float*)(w + lay.out_chi2);
-  d.out_ndf = (int32_t*)(w + lay.out_ndf);
-  d.scan_blocks = (unsigned long long*)(w + lay.scan_blocks);
-  d.hdr = (ResultHeader*)(w + lay.hdr);
-  d.grid_k = cfg->grid_hits_per_bin;
-  d.k5_mode = cfg->tracklet_schedule;
-  d.rho = k.rho;
-  d.R = R;
-  d.tcap = (uint32_t)caps.T;
-  d.max_tracks = (uint32_t)caps.MT;
-  d.max_track_clusters = caps.MC;
-  // pinned host buffers
+  // pinned host buffers, sized for the create-time capacities (later bindings are no larger)
+  t->host_caps = caps;
   if (hipHostMalloc((void**)&t->h_frame, lay.secs + caps.Smax * sizeof(SectorConst) - lay.row_off) != hipSuccess ||
-      hipHostMalloc((void**)&t->h_hdr, sizeof(ResultHeader)) != hipSuccess)
+      hipHostMalloc((void**)&t->h_hdr, sizeof(ResultHeader)) != hipSuccess ||
+      hipHostMalloc((void**)&t->h_rows, R * sizeof(RowConst)) != hipSuccess)
     return cleanup(fail(TPC_E_NOMEM, "hipHostMalloc staging"));
-  t->h_row_off = (uint32_t*)t->h_frame;
-  t->h_tile_off = (uint32_t*)(t->h_frame + (lay.tile_off - lay.row_off));
-  t->h_secs = (SectorConst*)(t->h_frame + (lay.secs - lay.row_off));
   const uint64_t out_bytes = lay.out_ndf + caps.MT * 4 - lay.out_sector;
   if (hipHostMalloc((void**)&t->h_out, out_bytes) != hipSuccess)
     return cleanup(fail(TPC_E_NOMEM, "hipHostMalloc outputs"));
-  if (hipMemcpy((void*)d.rows, t->rows.data(), R * sizeof(RowConst), hipMemcpyHostToDevice) != hipSuccess)
+  std::memcpy(t->h_rows, t->rows.data(), R * sizeof(RowConst));
+  carve(t);
+  t->home_ws = t->ws;
+  t->home_caps = caps;
+  t->home_lay = lay;
+  if (hipMemcpy((void*)t->d.rows, t->h_rows, R * sizeof(RowConst), hipMemcpyHostToDevice) != hipSuccess)
     return cleanup(fail(TPC_E_DEVICE, "upload row constants"));
   if (hipEventCreateWithFlags(&t->done, hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(TPC_E_DEVICE, "hipEventCreate"));
@@ -388,12 +416,67 @@ void tpc_tracker_destroy(tpc_tracker* t) {
   if (t->done) (void)hipEventDestroy(t->done);
   for (auto& e : t->ev)
     if (e) (void)hipEventDestroy(e);
-  if (t->own_ws && t->ws) (void)hipFree(t->ws);
+  if (t->own_ws && t->home_ws) (void)hipFree(t->home_ws);
   if (t->h_frame) (void)hipHostFree(t->h_frame);
   if (t->h_hdr) (void)hipHostFree(t->h_hdr);
   if (t->h_out) (void)hipHostFree(t->h_out);
+  if (t->h_rows) (void)hipHostFree(t->h_rows);
   if (t->own_stream && t->stream) (void)hipStreamDestroy(t->stream);
   delete t;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Capacities of a workspace binding for at most max_clusters / max_sectors: the
+// defaults for max_clusters, limited by what the tracker was created with.
+Caps bound_caps(const tpc_tracker* t, uint64_t max_clusters, uint32_t max_sectors) {
+  tpc_tracker_config c = t->cfg;
+  c.max_clusters = max_clusters;
+  c.max_sectors = max_sectors;
+  c.max_tracklets = c.max_tracks = c.max_track_clusters = 0;
+  Caps k = caps_of(c);
+  const Caps& h = t->host_caps;
+  k.T = std::min(k.T, h.T);
+  k.MT = std::min(k.MT, h.MT);
+  k.MC = std::min(k.MC, h.MC);
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t tpc_workspace_bytes_for(const tpc_tracker* t, uint64_t max_clusters, uint32_t max_sectors) {
+  if (!t || max_sectors < 1 || max_clusters >= (1ull << 31)) return 0;
+  if (max_clusters > t->host_caps.N || max_sectors > t->host_caps.Smax) return 0;
+  return layout_of(bound_caps(t, max_clusters, max_sectors)).total;
+}
+
+tpc_status tpc_tracker_bind_workspace(tpc_tracker* t, void* workspace, uint64_t workspace_bytes, uint64_t max_clusters,
+                                      uint32_t max_sectors) {
+  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
+  if (t->in_flight) return fail(TPC_E_BUSY, "a request is in flight");
+  if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(TPC_E_INVAL, "workspace NULL or not 256-byte aligned");
+  if (max_sectors < 1 || max_sectors > t->host_caps.Smax || max_clusters > t->host_caps.N)
+    return fail(TPC_E_INVAL, "capacities exceed those the tracker was created with");
+  const Caps k = bound_caps(t, max_clusters, max_sectors);   // the pinned host buffers hold at most these
+  const Layout lay = layout_of(k);
+  if (workspace_bytes < lay.total) return fail(TPC_E_INVAL, "workspace too small for these capacities");
+  HIP_TRY(hipSetDevice(t->device));
+  if (t->own_ws && t->home_ws) {
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    HIP_TRY(hipFree(t->home_ws));
+  }
+  t->own_ws = false;
+  t->home_ws = t->ws = (char*)workspace;
+  t->home_caps = t->caps = k;
+  t->home_lay = t->lay = lay;
+  carve(t);
+  // the row constants live in the workspace: upload them into the new one, in stream order
+  HIP_TRY(hipMemcpyAsync((void*)t->d.rows, t->h_rows, k.R * sizeof(RowConst), hipMemcpyHostToDevice, t->stream));
+  return TPC_OK;
 }
 
 }  // extern "C"
@@ -409,11 +492,11 @@ __global__ void k_begin(ResultHeader* h) {
   h->n_steps = 0;
 }
 
-std::string validate_frame(const tpc_tracker* t, const tpc_timeframe* f, uint32_t* max_row) {
+std::string validate_frame(const tpc_tracker* t, const Caps& caps, const tpc_timeframe* f, uint32_t* max_row) {
   if (!f) return "timeframe is NULL";
   if (f->n_rows != (uint32_t)t->cfg.n_rows) return "n_rows differs from the configuration";
-  if (f->n_sectors < 1 || f->n_sectors > t->caps.Smax) return "n_sectors out of range";
-  if (f->n_clusters > t->caps.N) return "n_clusters exceeds max_clusters";
+  if (f->n_sectors < 1 || f->n_sectors > caps.Smax) return "n_sectors out of range";
+  if (f->n_clusters > caps.N) return "n_clusters exceeds max_clusters";
   if (!f->row_offsets || !f->sector_z_lo || !f->sector_z_hi) return "row_offsets / sector z ranges are NULL";
   if (f->n_clusters && (!f->y || !f->z)) return "y / z is NULL";
   if (f->flags & ~1u) return "unknown flags";
@@ -436,17 +519,8 @@ std::string validate_frame(const tpc_tracker* t, const tpc_timeframe* f, uint32_
   return "";
 }
 
-}  // namespace
-
-extern "C" {
-
-tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t* request_id) {
-  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
-  if (t->in_flight) return fail(TPC_E_BUSY, "previous request not released");
-  uint32_t max_row = 0;
-  const std::string why = validate_frame(t, f, &max_row);
-  if (!why.empty()) return fail(TPC_E_INVAL, why);
-  HIP_TRY(hipSetDevice(t->device));
+// Enqueues C1..C7 of a validated frame on the tracker's current workspace binding.
+tpc_status enqueue(tpc_tracker* t, const tpc_timeframe* f, uint32_t max_row, uint64_t* request_id) {
   DevPtrs& d = t->d;
   const uint32_t S = f->n_sectors, R = f->n_rows, SR = S * R, N = (uint32_t)f->n_clusters;
   d.S = S;
@@ -537,6 +611,20 @@ tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t*
   t->cur_N = N;
   if (request_id) *request_id = t->cur_id;
   return TPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t* request_id) {
+  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
+  if (t->in_flight) return fail(TPC_E_BUSY, "previous request not released");
+  uint32_t max_row = 0;
+  const std::string why = validate_frame(t, t->home_caps, f, &max_row);
+  if (!why.empty()) return fail(TPC_E_INVAL, why);
+  HIP_TRY(hipSetDevice(t->device));
+  return enqueue(t, f, max_row, request_id);
 }
 
 tpc_status tpc_get_tracks(tpc_tracker* t, uint64_t request_id, int32_t blocking, tpc_tracks* out) {

@@ -23,6 +23,7 @@ TPC_ABI_VERSION = 1
 TPC_OK, TPC_E_INVAL, TPC_E_NOMEM, TPC_E_DEVICE, TPC_E_CAPACITY, TPC_E_NOTREADY, TPC_E_INPUT, TPC_E_BUSY = \
     0, -1, -2, -3, -4, -5, -6, -7
 TPC_IN_DEVICE, TPC_IN_HOST = 0, 1
+TPC_ERR_NONFINITE, TPC_ERR_TRACKLET_OVERFLOW, TPC_ERR_TRACK_OVERFLOW, TPC_ERR_CLUSTER_OVERFLOW = 1, 2, 4, 8
 (TPC_DBG_SORTED_ID, TPC_DBG_SORTED_YZ, TPC_DBG_BIN_START, TPC_DBG_ROW_DIMS, TPC_DBG_UP0, TPC_DBG_DOWN0, TPC_DBG_UP1,
  TPC_DBG_DOWN1, TPC_DBG_STARTS, TPC_DBG_TK_ROWHIT, TPC_DBG_TK_INFO, TPC_DBG_TK_PARAM, TPC_DBG_TK_COV,
  TPC_DBG_TK_CHI2) = range(1, 15)
@@ -31,9 +32,10 @@ PASS_NAMES = ("grid", "neighbours", "clean+starts", "tracklets", "select", "outp
 
 
 class TrackerError(RuntimeError):
-    def __init__(self, status, msg):
-        super().__init__(f"tpc status {status}: {msg}")
+    def __init__(self, status, msg, error_flags=0):
+        super().__init__(f"tpc status {status}: {msg}" + (f" (error_flags {error_flags:#x})" if error_flags else ""))
         self.status = status
+        self.error_flags = error_flags
 
 
 class _Config(C.Structure):
@@ -76,6 +78,7 @@ class _Tracks(C.Structure):
 
 
 EXPORTED = ("tpc_default_config", "tpc_workspace_bytes", "tpc_tracker_create", "tpc_tracker_destroy",
+            "tpc_workspace_bytes_for", "tpc_tracker_bind_workspace",
             "tpc_track_timeframe", "tpc_get_tracks", "tpc_get_tracks_device", "tpc_release", "tpc_last_error", "tpc_debug_copy",
             "tpc_set_timing", "tpc_get_pass_times", "tpc_set_tracklet_schedule")
 
@@ -98,6 +101,10 @@ def load():
     L.tpc_tracker_create.restype = C.c_int32
     L.tpc_tracker_create.argtypes = [P(_Config), P(C.c_void_p)]
     L.tpc_tracker_destroy.argtypes = [C.c_void_p]
+    L.tpc_workspace_bytes_for.restype = C.c_uint64
+    L.tpc_workspace_bytes_for.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32]
+    L.tpc_tracker_bind_workspace.restype = C.c_int32
+    L.tpc_tracker_bind_workspace.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint32]
     L.tpc_track_timeframe.restype = C.c_int32
     L.tpc_track_timeframe.argtypes = [C.c_void_p, P(_Frame), P(C.c_uint64)]
     L.tpc_get_tracks.restype = C.c_int32
@@ -119,9 +126,9 @@ def load():
     return L
 
 
-def _check(st):
+def _check(st, error_flags=0):
     if st != TPC_OK:
-        raise TrackerError(st, load().tpc_last_error().decode())
+        raise TrackerError(st, load().tpc_last_error().decode(), error_flags)
 
 
 def make_config(cfg: TrackerConfig, *, max_clusters, max_sectors=36, max_tracklets=0, max_tracks=0,
@@ -172,7 +179,10 @@ class Tracker:
     """One tracker on one GPU; workspace and stream come from torch."""
 
     def __init__(self, cfg: TrackerConfig | None = None, *, max_clusters, max_sectors=36, max_tracklets=0,
-                 max_tracks=0, max_track_clusters=0, device=0, stream=None, tracklet_schedule=0):
+                 max_tracks=0, max_track_clusters=0, device=0, stream=None, tracklet_schedule=0, workspace=None):
+        """``workspace``: optional (device address, bytes) of caller-owned memory to create the
+        tracker on (256-byte aligned, at least ``workspace_bytes`` of the configuration); by
+        default torch allocates it."""
         import torch
         self._torch = torch
         L = load()
@@ -187,9 +197,12 @@ class Tracker:
         nbytes = L.tpc_workspace_bytes(C.byref(c))
         if nbytes == 0:
             raise TrackerError(TPC_E_INVAL, "invalid tracker configuration")
-        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self._ws.data_ptr()
-        c.workspace = (base + 255) // 256 * 256
+        if workspace is not None and int(workspace[1]) >= nbytes:
+            self._ws = None
+            c.workspace = int(workspace[0])
+        else:
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            c.workspace = (self._ws.data_ptr() + 255) // 256 * 256
         c.workspace_bytes = nbytes
         # the tracker's own stream (default priority); each submit orders it after torch's current stream
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
@@ -239,9 +252,11 @@ class Tracker:
             self.stream.wait_event(self._ready)
             f.y, f.z = y.data_ptr(), z.data_ptr()
             f.flags = TPC_IN_DEVICE
-        self._inputs = (y, z, row_offsets, z_lo, z_hi)   # borrowed until the request completes
         rid = C.c_uint64()
         _check(load().tpc_track_timeframe(self._h, C.byref(f), C.byref(rid)))
+        # borrowed until the request completes; set only once the request is accepted, so a
+        # rejected submit (busy, invalid) leaves the in-flight request's inputs referenced
+        self._inputs = (y, z, row_offsets, z_lo, z_hi)
         return rid.value
 
     def get(self, rid, blocking=True):
@@ -249,7 +264,7 @@ class Tracker:
         st = load().tpc_get_tracks(self._h, rid, 1 if blocking else 0, C.byref(t))
         if st == TPC_E_NOTREADY:
             return None
-        _check(st)
+        _check(st, t.error_flags)
         n, nc = t.n_tracks, t.n_track_clusters
 
         def arr(ptr, count, dt):
@@ -298,6 +313,18 @@ class Tracker:
         y = torch.from_numpy(ev.y).to(self.device)
         z = torch.from_numpy(ev.z).to(self.device)
         return self.track(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+
+    # ---- per-request workspaces ----
+    def workspace_bytes_for(self, max_clusters, max_sectors):
+        """Device bytes of a workspace binding for these capacities (0 if beyond the create-time ones)."""
+        return int(load().tpc_workspace_bytes_for(self._h, int(max_clusters), int(max_sectors)))
+
+    def bind_workspace(self, address, nbytes, max_clusters, max_sectors):
+        """Move the tracker onto caller-owned device memory at ``address`` (256-byte aligned) sized for
+        the given capacities; the caller keeps that memory alive while requests run on it."""
+        _check(load().tpc_tracker_bind_workspace(self._h, C.c_void_p(int(address)), int(nbytes), int(max_clusters),
+                                                 int(max_sectors)))
+        self._ws = None   # the create-time workspace is no longer used
 
     # ---- introspection ----
     def debug(self, what, dtype):

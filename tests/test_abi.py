@@ -76,3 +76,29 @@ def test_null_arguments_rejected(lib):
     assert lib.tpc_track_timeframe(None, None, None) == trk.TPC_E_INVAL
     assert lib.tpc_release(None, 1) == trk.TPC_E_INVAL
     assert lib.tpc_set_tracklet_schedule(None, 1) == trk.TPC_E_INVAL
+
+
+def test_rejected_submit_keeps_the_inflight_inputs(monkeypatch):
+    """A submit that the library rejects (here: busy) must not drop the references
+    that keep the in-flight request's input arrays alive."""
+    class FakeLib:
+        def tpc_track_timeframe(self, h, f, rid):
+            return trk.TPC_E_BUSY
+
+        def tpc_last_error(self):
+            return b"previous request not released"
+
+    monkeypatch.setattr(trk, "_lib", FakeLib())
+    t = trk.Tracker.__new__(trk.Tracker)
+    t.R = 152
+    t._h = C.c_void_p(1)
+    inflight = object()
+    t._inputs = inflight
+    y = np.zeros(4, np.float32)
+    offs = np.zeros(153, np.uint32)
+    offs[-1] = 4
+    with pytest.raises(trk.TrackerError) as ex:
+        t.submit(y, y, offs, [0.0], [250.0], host=True)
+    assert ex.value.status == trk.TPC_E_BUSY
+    assert t._inputs is inflight
+    t._h = C.c_void_p()
