@@ -1,15 +1,19 @@
-"""Benchmark: TPC clusters/s tracked on one MI355X (plain path, one time frame per step).
+"""Benchmark: TPC clusters/s tracked on one MI355X, time-frame latency against the plain path.
 
 One step = steps C1..C7 over the whole workload: enqueue the time frame
 (device-resident clusters), wait for it (tracks stay in HBM; the counts come
 back to the host), release.  A second loop measures the same with the track
-arrays copied to host memory ("e2e_host_copy").  The default workload is one
-central heavy-ion-like event in all 36 sectors (seeded synthetic data, about
-1.28M clusters).
+arrays copied to host memory ("e2e_host_copy").  The default workload is the
+32-orbit continuous-readout time frame at 50 kHz (seeded synthetic data,
+about 10M clusters in 36 sectors).
 
-Prints one JSON line with the headline value, per-step latency percentiles,
-per-pass HIP-event times, the roofline entry of the dominant kernel and the
-FP64 oracle timed on the host cores on a bounded sample.
+Beside the headline the line carries: per-frame latency of the plain
+per-sector launches on the same frame; the 512 uneven chunks in one batched
+request; a short serving trace (Poisson arrivals at 200 requests/s, 70% pp of
+1-4 orbits, 30% heavy-ion of 1-32 orbits) served with continuous batching
+under a 200 GB budget against the plain per-sector path; the roofline entry of
+the dominant kernel; the FP64 oracle timed on the host cores on a bounded
+sample, with the host CPU model.
 """
 from __future__ import annotations
 
@@ -58,6 +62,20 @@ def pmc_traffic(workload, pass_name):
                 return None
     fw = PMC_TRAFFIC.get(workload, {}).get(pass_name)
     return None if fw is None else round((fw[0] + fw[1]) * MIB)
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def log(msg):
@@ -162,35 +180,58 @@ def tr_schedule_rowsync(schedule, ev):
     return int(np.diff(np.asarray(ev.row_offsets, np.int64)).max()) <= 320
 
 
-def serve_main(args):
-    """Plain path (one slot, FIFO) versus served path (several slots) on the same trace."""
+def serve_compare(dev, duration_s, rate_hz, slots, budget_bytes, plain_deadline_s, seed=5):
+    """The serving trace (Poisson arrivals, 70% pp of 1-4 orbits, 30% heavy-ion of 1-32 orbits) run twice:
+    the plain path (one frame at a time, per-sector launches) and the server (continuous batching over
+    ``slots`` slots under an HBM budget).  Returns a dict for the JSON line."""
     import torch
     from paper_2502_09138_amd import serving
-    dev = torch.device("cuda", 0)
+    from paper_2502_09138_amd.tracker import Tracker
     log("serve: generating the frame pool")
     pool = serving.make_pool(dev, log=log)
-    trace = serving.make_trace(pool, rate_hz=args.rate, duration_s=args.serve, seed=5)
+    trace = serving.make_trace(pool, rate_hz=rate_hz, duration_s=duration_s, seed=seed)
     cap = max(f.n_clusters for f in pool)
     res = {}
-    for label, slots in (("plain", 1), ("served", args.slots)):
-        srv = serving.Server(max_clusters=cap, slots=slots)
-        srv.run(pool, trace[:min(20, len(trace))])           # warm-up on the head of the trace
-        log(f"serve: {label} with {srv.slots} slot(s), {len(trace)} requests over {args.serve} s")
-        rec, _, wall = srv.run(pool, trace)
-        res[label] = dict(serving.summarize(rec, wall, args.serve), slots=srv.slots)
-        srv.close()
-        log(f"serve: {label}: {res[label]}")
+    tr = Tracker(max_clusters=cap)
+    serving.run_plain_per_sector(tr, pool, trace[:3])                      # warm-up
+    log(f"serve: plain per-sector path, {len(trace)} requests over {duration_s} s")
+    rec, _, wall = serving.run_plain_per_sector(tr, pool, trace, deadline_s=plain_deadline_s)
+    res["plain_per_sector"] = serving.summarize(rec, wall, duration_s)
+    tr.close()
+    del tr
+    torch.cuda.empty_cache()
+    log(f"serve: plain: {res['plain_per_sector']}")
+    srv = serving.Server(max_clusters=cap, slots=slots, hbm_budget_bytes=budget_bytes)
+    srv.run(pool, trace[:min(20, len(trace))])                              # warm-up on the head of the trace
+    log(f"serve: served, {srv.slots} slots, budget {budget_bytes / 2**30:.0f} GiB")
+    rec, _, wall = srv.run(pool, trace)
+    res["served"] = dict(serving.summarize(rec, wall, duration_s), slots=srv.slots, budget_gib=budget_bytes / 2**30,
+                         peak_in_use_gib=round(srv.pool.peak / 2**30, 3))
+    srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    log(f"serve: served: {res['served']}")
+    res["trace"] = {"rate_hz": rate_hz, "duration_s": duration_s, "requests": len(trace), "pp_fraction": 0.7,
+                    "pp_orbits": "1-4", "hi_orbits": "1-32 (frames of 1, 2, 4, 8, 16, 32 orbits)", "seed": seed,
+                    "pool": [f"{f.name}:{f.n_clusters}" for f in pool],
+                    "plain_deadline_s": plain_deadline_s}
+    return res
+
+
+def serve_main(args):
+    import torch
+    dev = torch.device("cuda", 0)
+    res = serve_compare(dev, args.serve, args.rate, args.slots, int(args.budget_gib * 2**30), args.plain_deadline)
     out = {
-        "metric": "p50/p99 time-frame latency, plain vs served, Poisson trace",
+        "metric": "p50/p99 time-frame latency, plain per-sector launches vs continuous batching, Poisson trace",
         "value": round(res["served"]["p99_ms"], 3),
         "unit": "ms (p99, served)",
         "n_gpus": 1,
         "higher_is_better": False,
         "data": "synthetic",
         "dtype": "f32",
-        "config": {"workload": "poisson_trace", "rate_hz": args.rate, "duration_s": args.serve,
-                   "pp_fraction": 0.8, "pool": [f"{f.name}:{f.n_clusters}" for f in pool]},
-        "plain": res["plain"],
+        "config": {"workload": "serving_trace", **res["trace"]},
+        "plain_per_sector": res["plain_per_sector"],
         "served": res["served"],
     }
     print(json.dumps(out), flush=True)
@@ -201,7 +242,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="central_event")
+    ap.add_argument("--workload", default="time_frame")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", type=int, default=0,
@@ -212,10 +253,16 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this size first (PMC byte-counter calibration)")
     ap.add_argument("--serve", type=float, default=0.0,
-                    help="instead of the plain bench: serve a Poisson trace of this many seconds with one slot (plain "
-                         "path) and with --slots slots, report p50/p99 latency and clusters/s of both")
+                    help="instead of the plain bench: serve a Poisson trace of this many seconds on the plain "
+                         "per-sector path and with continuous batching, report p50/p99 latency and clusters/s of both")
     ap.add_argument("--slots", type=int, default=6)
-    ap.add_argument("--rate", type=float, default=800.0, help="trace arrival rate (requests/s) for --serve")
+    ap.add_argument("--rate", type=float, default=200.0, help="trace arrival rate (requests/s)")
+    ap.add_argument("--budget-gib", type=float, default=200.0, help="HBM budget of the server")
+    ap.add_argument("--plain-deadline", type=float, default=30.0,
+                    help="wall seconds after which the plain path stops starting new frames")
+    ap.add_argument("--serve-extra", type=float, default=1.0,
+                    help="seconds of serving trace in the default run's extras (0 = none)")
+    ap.add_argument("--quick", action="store_true", help="headline only: no per-sector, chunk or serving extras")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sectors and time frames "
@@ -363,12 +410,67 @@ def main():
         "roofline": roof.get(dominant, roof["tracklets"]),
         "roofline_passes": roof,
     }
+    k12 = (K1_BYTES_PER_CLUSTER + K2_BYTES_PER_CLUSTER) * N / ((pass_ms["grid"] + pass_ms["neighbours"]) * 1e-3) / 1e9
+    rec["k1_k2_hbm"] = {"achieved": round(k12, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(k12 / HBM_PEAK_GBS, 5),
+                        "note": "grid and neighbour passes together: algorithmic bytes (22 + 18 B per cluster) over "
+                                "their summed HIP-event times"}
+    if not args.quick and args.mode == "batched":
+        # the same frame as one request per sector (the plain path), frame latency and throughput
+        ps = []
+        for k in range(6):
+            s0 = time.perf_counter()
+            for sec, a, b, ro in spans:
+                rid = tr.submit(y[a:b], z[a:b], ro, zlo[sec:sec + 1], zhi[sec:sec + 1])
+                tr.get_device(rid)
+                tr.release(rid)
+            if k:                       # the first frame warms up the per-sector shapes
+                ps.append(time.perf_counter() - s0)
+        rec["per_sector_launches"] = {
+            "value": round(N * len(ps) / sum(ps), 1), "unit": "clusters/s",
+            "latency_ms": {"p50": round(1e3 * float(np.percentile(ps, 50)), 4),
+                           "p99": round(1e3 * float(np.percentile(ps, 99)), 4)},
+            "frames": len(ps), "speedup_of_batched": round(float(np.median(ps)) / (elapsed / args.steps), 2),
+            "note": f"the same frame as {ev.n_sectors} requests of one sector each, issued back to back"}
+        log(f"bench: per-sector launches: {rec['per_sector_launches']}")
     tr.close()
+    del tr, y, z
+    torch.cuda.empty_cache()
+    if not args.quick and args.mode == "batched" and args.workload != "uneven_chunks":
+        log("bench: generating uneven_chunks")
+        evc, _ = make_workload("uneven_chunks")
+        yc = torch.from_numpy(evc.y).to(dev)
+        zc = torch.from_numpy(evc.z).to(dev)
+        trc = Tracker(default_config(), max_clusters=evc.n_clusters, max_sectors=evc.n_sectors,
+                      tracklet_schedule=args.schedule)
+        for _ in range(2):
+            rid = trc.submit(yc, zc, evc.row_offsets, evc.sector_z_lo, evc.sector_z_hi)
+            trc.get_device(rid)
+            trc.release(rid)
+        torch.cuda.synchronize()
+        tc = []
+        for _ in range(5):
+            s0 = time.perf_counter()
+            rid = trc.submit(yc, zc, evc.row_offsets, evc.sector_z_lo, evc.sector_z_hi)
+            cc = trc.get_device(rid)
+            trc.release(rid)
+            tc.append(time.perf_counter() - s0)
+        rec["uneven_chunks"] = {"value": round(evc.n_clusters * len(tc) / sum(tc), 1), "unit": "clusters/s",
+                                "ms_per_step": round(1e3 * float(np.mean(tc)), 4), "n_clusters": evc.n_clusters,
+                                "n_chunks": evc.n_sectors, "tracks": cc["n_tracks"],
+                                "note": "512 sector-sized chunks of log-uniform occupancy (1k-200k), one batched request"}
+        log(f"bench: uneven_chunks: {rec['uneven_chunks']}")
+        trc.close()
+        del trc, yc, zc, evc
+        torch.cuda.empty_cache()
+    if not args.quick and args.serve_extra > 0:
+        rec["serving"] = serve_compare(dev, args.serve_extra, args.rate, args.slots, int(args.budget_gib * 2**30),
+                                       args.plain_deadline)
     rec["achievable_copy"] = copy_bandwidth(torch, dev)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         cb = cpu_baseline(ev, args.cpu_budget)
         rec["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        rec["cpu_baseline"]["host_cpu"] = host_cpu()
         log("bench: timing the oracle on all host cores")
         rec["cpu_baseline_all_cores"] = cpu_baseline_pool(ev, args.cpu_budget)
     else:
