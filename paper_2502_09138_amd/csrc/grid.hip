@@ -16,11 +16,15 @@ namespace {
 constexpr int kThreads = 256;
 constexpr uint32_t kLdsRowCap = 4096;        // rows up to this many hits run from LDS
 
-struct RowArrays {   // cnt[nb+1], key[n], slot[n], tmp[n]
+// cnt[nb+1] (32-bit: bin counts, then bin starts); key[n], slot[n], tmp[n] as
+// 16-bit values (bin index < nb <= 65535, rank inside a bin and local id < n <=
+// 65535), which halves the LDS a row needs and so doubles the rows resident
+// per CU.
+struct RowArrays {
   uint32_t* cnt;
-  uint32_t* key;
-  uint32_t* slot;
-  uint32_t* tmp;
+  uint16_t* key;
+  uint16_t* slot;
+  uint16_t* tmp;
 };
 
 __device__ void grid_row(const DevPtrs& d, uint32_t sr, const RowArrays& A, uint32_t* wsum) {
@@ -47,8 +51,8 @@ __device__ void grid_row(const DevPtrs& d, uint32_t sr, const RowArrays& A, uint
     const int iy = bin1(yv, rc.y_lo, rc.inv_wy, ny);
     const int iz = bin1(zv, sc.z_lo, sc.inv_wz, nz);
     const uint32_t b = (uint32_t)(iz * ny + iy);
-    A.key[j] = b;
-    A.slot[j] = atomicAdd(&A.cnt[b], 1u);
+    A.key[j] = (uint16_t)b;
+    A.slot[j] = (uint16_t)atomicAdd(&A.cnt[b], 1u);
   }
   if (__any(bad) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&d.hdr->error_flags, 1u);
   __syncthreads();
@@ -60,7 +64,7 @@ __device__ void grid_row(const DevPtrs& d, uint32_t sr, const RowArrays& A, uint
     const uint32_t b = A.key[j];
     const uint32_t b0 = A.cnt[b], b1 = A.cnt[b + 1];
     uint32_t rank = 0;
-    for (uint32_t q = b0; q < b1; ++q) rank += A.tmp[q] < j;
+    for (uint32_t q = b0; q < b1; ++q) rank += (uint32_t)A.tmp[q] < j;
     const uint32_t out = a + b0 + rank;
     d.sid[out] = a + j;
     d.syz[out] = make_float2(d.y[a + j], d.z[a + j]);
@@ -73,13 +77,19 @@ __device__ void grid_row(const DevPtrs& d, uint32_t sr, const RowArrays& A, uint
   for (uint32_t t = d.tile_off[sr] + threadIdx.x; t < d.tile_off[sr + 1]; t += blockDim.x) d.tile_sr[t] = sr;
 }
 
+// LDS of a row of up to cap hits: cnt_words 32-bit bin counts (nb + 1 <= cap / K + 1,
+// rounded to an even count so the 16-bit arrays start 4-byte aligned), then
+// three 16-bit arrays of cap entries.
+__host__ __device__ inline uint32_t cnt_words(uint32_t cap, int k) { return ((cap / (uint32_t)k + 2) + 1u) & ~1u; }
+
 __global__ void __launch_bounds__(kThreads) k_grid_lds(DevPtrs d, uint32_t cap) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t wsum[kThreads / kWave];
   const uint32_t sr = blockIdx.x;
   const uint32_t n = d.row_off[sr + 1] - d.row_off[sr];
   if (n > cap) return;            // handled by k_grid_global
-  RowArrays A{lds, lds + cap + 2, lds + 2 * cap + 2, lds + 3 * cap + 2};
+  uint16_t* h = reinterpret_cast<uint16_t*>(lds + cnt_words(cap, d.grid_k));
+  RowArrays A{lds, h, h + cap, h + 2 * cap};
   grid_row(d, sr, A, wsum);
 }
 
@@ -93,7 +103,8 @@ __global__ void __launch_bounds__(kThreads) k_grid_global(DevPtrs d, uint32_t ca
   const uint32_t a = d.row_off[sr];
   const uint32_t n = d.row_off[sr + 1] - a;
   if (n <= cap) return;
-  RowArrays A{d.bin_start + bin_base(d, sr), (uint32_t*)d.up0 + a, (uint32_t*)d.down0 + a, (uint32_t*)d.up1 + a};
+  RowArrays A{d.bin_start + bin_base(d, sr), reinterpret_cast<uint16_t*>(d.up0 + a),
+              reinterpret_cast<uint16_t*>(d.down0 + a), reinterpret_cast<uint16_t*>(d.up1 + a)};
   grid_row(d, sr, A, wsum);
 }
 
@@ -102,7 +113,7 @@ __global__ void __launch_bounds__(kThreads) k_grid_global(DevPtrs d, uint32_t ca
 void launch_grid(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s) {
   if (d.SR == 0) return;
   const uint32_t cap = max_row_hits < kLdsRowCap ? max_row_hits : kLdsRowCap;
-  const size_t lds = (size_t)(4 * cap + 2) * sizeof(uint32_t);
+  const size_t lds = (size_t)cnt_words(cap, d.grid_k) * sizeof(uint32_t) + (size_t)3 * cap * sizeof(uint16_t);
   hipLaunchKernelGGL(k_grid_lds, dim3(d.SR), dim3(kThreads), lds, s, d, cap);
   if (max_row_hits > kLdsRowCap) hipLaunchKernelGGL(k_grid_global, dim3(d.SR), dim3(kThreads), 0, s, d, cap);
 }
