@@ -216,6 +216,23 @@ typedef struct {
  * nothing. */
 tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* tf, uint64_t* request_id);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same as
+ * tpc_track_timeframe, but the request's whole device workspace is carved
+ * from one fixed array of TPC_SCRATCH_BYTES per device inside the library,
+ * not from the tracker's own workspace, and the call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).  Frames whose workspace
+ * (tpc_workspace_bytes_for their cluster and sector counts) exceeds the array
+ * are rejected with TPC_E_INVAL and a message; that is about 0.85M clusters
+ * at the default capacities (about 300 B per cluster).  The array is shared by
+ * every tracker on the device and keeps the last request's contents: requests
+ * that overlap on one device race, so issue the next one only after the
+ * previous one was released.  Results are read with tpc_get_tracks (host
+ * copies) or tpc_get_tracks_device (views into the array, valid until the next
+ * call of this function on the device).  A later tpc_track_timeframe runs on
+ * the tracker's own workspace again. */
+#define TPC_SCRATCH_BYTES (256ull << 20)
+tpc_status tpc_track_timeframe_scratch(tpc_tracker* t, const tpc_timeframe* tf, uint64_t* request_id);
 
 typedef struct {
   uint32_t n_tracks;

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -37,6 +38,14 @@ tpc_status fail(tpc_status st, const std::string& msg) {
   } while (0)
 
 constexpr double kCB = 0.00299792458;
+
+// Device scratch of the allocation-free entry point tpc_track_timeframe_scratch:
+// a request's whole workspace (grid, links, tracklets, outputs) carved from one
+// file-scope array of each device, so that call allocates nothing.  Its host
+// address is a stand-in: host code uses only the device address looked up with
+// hipGetSymbolAddress (g_scratch_ptr, per device).
+constexpr uint64_t kScratchBytes = TPC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kSelectTileWords = 12288;     // 48 KB of LDS per selector tile at most
 constexpr uint32_t kSelectTilePreferred = 4096;  // 16 KB: multi-row tiles above this keep too few tiles resident
@@ -150,6 +159,22 @@ std::string validate_config(const tpc_tracker_config* c) {
   return "";
 }
 
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of this device's scratch array (looked up once per device, with that device current).
+tpc_status scratch_lookup(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return fail(TPC_E_INVAL, "device ordinal beyond the scratch table");
+  if (g_scratch_ptr[device]) return TPC_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return fail(TPC_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return TPC_OK;
+}
+
 }  // namespace
 
 struct tpc_tracker {
@@ -158,10 +183,11 @@ struct tpc_tracker {
   Caps caps{};        // capacities of the current workspace binding
   Layout lay{};
   Caps host_caps{};   // capacities the pinned host buffers are sized for (create time)
-  // the workspace requests run on (create or bind_workspace)
+  // the workspace requests run on unless they use the device scratch (create or bind_workspace)
   char* home_ws = nullptr;
   Caps home_caps{};
   Layout home_lay{};
+  bool on_scratch = false;
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -398,6 +424,7 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   t->home_lay = lay;
   if (hipMemcpy((void*)t->d.rows, t->h_rows, R * sizeof(RowConst), hipMemcpyHostToDevice) != hipSuccess)
     return cleanup(fail(TPC_E_DEVICE, "upload row constants"));
+  if (const tpc_status st = scratch_lookup(cfg->device); st != TPC_OK) return cleanup(st);
   if (hipEventCreateWithFlags(&t->done, hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(TPC_E_DEVICE, "hipEventCreate"));
   for (int i = 0; i <= kPasses; ++i)
@@ -473,6 +500,7 @@ tpc_status tpc_tracker_bind_workspace(tpc_tracker* t, void* workspace, uint64_t 
   t->home_ws = t->ws = (char*)workspace;
   t->home_caps = t->caps = k;
   t->home_lay = t->lay = lay;
+  t->on_scratch = false;
   carve(t);
   // the row constants live in the workspace: upload them into the new one, in stream order
   HIP_TRY(hipMemcpyAsync((void*)t->d.rows, t->h_rows, k.R * sizeof(RowConst), hipMemcpyHostToDevice, t->stream));
@@ -624,6 +652,37 @@ tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* f, uint64_t*
   const std::string why = validate_frame(t, t->home_caps, f, &max_row);
   if (!why.empty()) return fail(TPC_E_INVAL, why);
   HIP_TRY(hipSetDevice(t->device));
+  if (t->on_scratch) {   // back on the tracker's own workspace (its row constants are still there)
+    t->ws = t->home_ws;
+    t->caps = t->home_caps;
+    t->lay = t->home_lay;
+    t->on_scratch = false;
+    carve(t);
+  }
+  return enqueue(t, f, max_row, request_id);
+}
+
+tpc_status tpc_track_timeframe_scratch(tpc_tracker* t, const tpc_timeframe* f, uint64_t* request_id) {
+  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
+  if (t->in_flight) return fail(TPC_E_BUSY, "previous request not released");
+  uint32_t max_row = 0;
+  const std::string why = validate_frame(t, t->host_caps, f, &max_row);
+  if (!why.empty()) return fail(TPC_E_INVAL, why);
+  const Caps k = bound_caps(t, std::max<uint64_t>(1, f->n_clusters), f->n_sectors);
+  const Layout lay = layout_of(k);
+  if (lay.total > kScratchBytes)
+    return fail(TPC_E_INVAL, "the frame needs " + std::to_string(lay.total) + " bytes of device scratch; the scratch holds " +
+                                 std::to_string(kScratchBytes));
+  void* ptr = t->device < kMaxDevices ? g_scratch_ptr[t->device] : nullptr;
+  if (!ptr) return fail(TPC_E_DEVICE, "device scratch address not looked up");
+  HIP_TRY(hipSetDevice(t->device));
+  t->ws = (char*)ptr;
+  t->caps = k;
+  t->lay = lay;
+  t->on_scratch = true;
+  carve(t);
+  // another tracker may have used the scratch since: its row constants go in with every request
+  HIP_TRY(hipMemcpyAsync((void*)t->d.rows, t->h_rows, k.R * sizeof(RowConst), hipMemcpyHostToDevice, t->stream));
   return enqueue(t, f, max_row, request_id);
 }
 

@@ -78,7 +78,7 @@ class _Tracks(C.Structure):
 
 
 EXPORTED = ("tpc_default_config", "tpc_workspace_bytes", "tpc_tracker_create", "tpc_tracker_destroy",
-            "tpc_workspace_bytes_for", "tpc_tracker_bind_workspace",
+            "tpc_workspace_bytes_for", "tpc_tracker_bind_workspace", "tpc_track_timeframe_scratch",
             "tpc_track_timeframe", "tpc_get_tracks", "tpc_get_tracks_device", "tpc_release", "tpc_last_error", "tpc_debug_copy",
             "tpc_set_timing", "tpc_get_pass_times", "tpc_set_tracklet_schedule")
 
@@ -107,6 +107,8 @@ def load():
     L.tpc_tracker_bind_workspace.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint32]
     L.tpc_track_timeframe.restype = C.c_int32
     L.tpc_track_timeframe.argtypes = [C.c_void_p, P(_Frame), P(C.c_uint64)]
+    L.tpc_track_timeframe_scratch.restype = C.c_int32
+    L.tpc_track_timeframe_scratch.argtypes = [C.c_void_p, P(_Frame), P(C.c_uint64)]
     L.tpc_get_tracks.restype = C.c_int32
     L.tpc_get_tracks.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, P(_Tracks)]
     L.tpc_get_tracks_device.restype = C.c_int32
@@ -225,8 +227,9 @@ class Tracker:
             pass
 
     # ---- requests ----
-    def submit(self, y, z, row_offsets, z_lo, z_hi, *, host=False):
-        """Enqueue one time frame; y/z are CUDA float32 tensors (or numpy with host=True)."""
+    def submit(self, y, z, row_offsets, z_lo, z_hi, *, host=False, scratch=False):
+        """Enqueue one time frame; y/z are CUDA float32 tensors (or numpy with host=True).  scratch=True
+        uses the allocation-free entry point (the library's fixed device scratch array)."""
         row_offsets = np.ascontiguousarray(row_offsets, np.uint32)
         z_lo = np.ascontiguousarray(z_lo, np.float32)
         z_hi = np.ascontiguousarray(z_hi, np.float32)
@@ -253,7 +256,8 @@ class Tracker:
             f.y, f.z = y.data_ptr(), z.data_ptr()
             f.flags = TPC_IN_DEVICE
         rid = C.c_uint64()
-        _check(load().tpc_track_timeframe(self._h, C.byref(f), C.byref(rid)))
+        entry = load().tpc_track_timeframe_scratch if scratch else load().tpc_track_timeframe
+        _check(entry(self._h, C.byref(f), C.byref(rid)))
         # borrowed until the request completes; set only once the request is accepted, so a
         # rejected submit (busy, invalid) leaves the in-flight request's inputs referenced
         self._inputs = (y, z, row_offsets, z_lo, z_hi)
@@ -299,8 +303,8 @@ class Tracker:
         _check(load().tpc_release(self._h, rid))
         self._inputs = None
 
-    def track(self, y, z, row_offsets, z_lo, z_hi, *, host=False):
-        rid = self.submit(y, z, row_offsets, z_lo, z_hi, host=host)
+    def track(self, y, z, row_offsets, z_lo, z_hi, *, host=False, scratch=False):
+        rid = self.submit(y, z, row_offsets, z_lo, z_hi, host=host, scratch=scratch)
         try:
             return self.get(rid)
         finally:
