@@ -43,6 +43,8 @@ class _Cfg(C.Structure):
         ("gate_nsigma", C.c_double), ("win_cap", C.c_double), ("edge_margin", C.c_double),
         ("max_miss", C.c_int32), ("min_tracklet_hits", C.c_int32), ("min_track_hits", C.c_int32),
         ("min_owned_frac", C.c_double),
+        ("merge_dy", C.c_double), ("merge_dz", C.c_double), ("merge_dsinphi", C.c_double),
+        ("merge_dtanl", C.c_double), ("merge_dqpt", C.c_double),
     ]
 
 
@@ -66,6 +68,13 @@ def lib():
             getattr(L, f).argtypes = [vp]
             getattr(L, f).restype = C.c_int
         L.orc_run_construct.argtypes = [vp, u32p, C.c_uint64]
+        L.orc_merge_run.restype = vp
+        L.orc_merge_run.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.orc_merge_destroy.argtypes = [vp]
+        L.orc_merge_get.restype = C.c_uint64
+        L.orc_merge_get.argtypes = [vp, C.c_int, vp, C.c_uint64]
+        L.orc_rotate.restype = C.c_int
+        L.orc_rotate.argtypes = [C.c_double, dp, C.c_double, C.c_double, dp, dp, dp]
         L.orc_get.restype = C.c_uint64
         L.orc_get.argtypes = [vp, C.c_int, vp, C.c_uint64]
         L.orc_propagate.restype = C.c_int
@@ -197,6 +206,42 @@ class Run:
             tk_chi2=self.get(ORC_TK_CHI2, np.float64), trk_tracklet=self.get(ORC_TRK_TRACKLET, np.uint32),
             trk_first=self.get(ORC_TRK_FIRST, np.uint32), trk_clusters=self.get(ORC_TRK_CLUSTERS, np.uint32))
         return out
+
+
+ORC_M_NEXT, ORC_M_HEAD, ORC_M_HEADS, ORC_M_NSEG, ORC_M_PARAM, ORC_M_COV, ORC_M_CHI2, ORC_M_NDF, ORC_M_FIRST, \
+    ORC_M_CLUSTERS = range(1, 11)
+
+
+def merge(run, sector_phys=None):
+    """C8 sector merger + C9 refit on the C7 tracks of a finished run; returns a dict of arrays.
+    sector_phys: physical sector (0..35) of each of the run's sectors, -1 = no neighbours."""
+    sp = None if sector_phys is None else np.ascontiguousarray(sector_phys, np.int32)
+    h = lib().orc_merge_run(run.h, None if sp is None else _ptr(sp, C.c_int32))
+
+    def get(what, dt):
+        n = lib().orc_merge_get(h, what, None, 0)
+        out = np.empty(n // np.dtype(dt).itemsize, dt)
+        if n:
+            lib().orc_merge_get(h, what, out.ctypes.data_as(C.c_void_p), n)
+        return out
+
+    try:
+        return dict(next=get(ORC_M_NEXT, np.int32), head=get(ORC_M_HEAD, np.int32), heads=get(ORC_M_HEADS, np.uint32),
+                    nseg=get(ORC_M_NSEG, np.int32), param=get(ORC_M_PARAM, np.float64).reshape(-1, 5),
+                    cov=get(ORC_M_COV, np.float64).reshape(-1, 15), chi2=get(ORC_M_CHI2, np.float64),
+                    ndf=get(ORC_M_NDF, np.int32), first=get(ORC_M_FIRST, np.uint32),
+                    clusters=get(ORC_M_CLUSTERS, np.uint32))
+    finally:
+        lib().orc_merge_destroy(h)
+
+
+def rotate(x, p, d, bz):
+    p = np.ascontiguousarray(p, np.float64)
+    xo = C.c_double()
+    q = np.zeros(5)
+    J = np.zeros(25)
+    rc = lib().orc_rotate(x, _ptr(p, C.c_double), d, bz, C.byref(xo), _ptr(q, C.c_double), _ptr(J, C.c_double))
+    return rc, xo.value, q, J.reshape(5, 5)
 
 
 def propagate(p, x1, x2, bz, s_max=0.99):

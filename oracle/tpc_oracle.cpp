@@ -665,6 +665,257 @@ int orc_run_select(orc_run* r) {
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// C8 sector merger and C9 refit of merged chains (on the C7 tracks of a run).
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Rotation of a state at x from the frame of azimuth a into the frame of
+// azimuth a + d, at the same point in space, with its first-order Jacobian on
+// the new plane x' = const through that point (C8.1).  Fails unless the track
+// moves outward in the new frame (cos phi' > 0).
+bool rotate(double x, const double* p, double d, double bk, double* xo, double* q, double J[5][5]) {
+  const double cd = std::cos(d), sd = std::sin(d);
+  const double s = p[2], c = std::sqrt((1.0 - s) * (1.0 + s));
+  const double s2 = s * cd - c * sd, c2 = c * cd + s * sd;   // sin, cos of phi - d
+  if (!(c2 > 0.0)) return false;
+  *xo = x * cd + p[0] * sd;
+  q[0] = -x * sd + p[0] * cd;
+  q[1] = p[1];
+  q[2] = s2;
+  q[3] = p[3];
+  q[4] = p[4];
+  if (J) {
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) J[i][j] = (i == j) ? 1.0 : 0.0;
+    J[0][0] = c / c2;
+    J[1][0] = -p[3] * sd / c2;
+    J[2][0] = -bk * p[4] * sd;
+    J[2][2] = c2 / c;
+  }
+  return true;
+}
+
+double radius_of(double x, double y) { return std::sqrt(x * x + y * y); }
+
+struct MergeTrack {
+  uint32_t sector;       // index in the run
+  int32_t phys;          // physical sector 0..35, -1: no neighbours
+  double x;              // x_ref
+  double p[5], C[15];
+  double r_in;           // global radius of the innermost point
+  uint32_t first, n;     // clusters in trk_clusters
+};
+
+}  // namespace
+
+struct orc_merge {
+  std::vector<int32_t> next, prev, head;       // per track: successor, predecessor, chain head
+  std::vector<uint32_t> heads;                 // chain heads in ascending track index
+  std::vector<double> param, cov, chi2;        // per head: refit result (single-segment chains: C5 result)
+  std::vector<int32_t> ndf, nseg;
+  std::vector<uint32_t> first, clusters;       // per head: merged cluster list (input ids, chain order)
+};
+
+namespace {
+
+// C8.2 match score of t followed by u (both tracks of the run); false if no match.
+bool match_pair(const orc_run* r, const MergeTrack& a, const MergeTrack& b, double* score) {
+  const orc_config& c = r->cfg;
+  if (!(b.r_in > a.r_in)) return false;
+  const int side_a = a.phys / 18, side_b = b.phys / 18;
+  if (side_a != side_b) return false;
+  const int ia = a.phys % 18, ib = b.phys % 18;
+  int step = ib - ia;
+  if (step == 17) step = -1;
+  if (step == -17) step = 1;
+  if (step != 1 && step != -1) return false;
+  double xr, q[5];
+  if (!rotate(a.x, a.p, step * (20.0 * kPi / 180.0), r->bk, &xr, q, nullptr)) return false;
+  double q2[5];
+  if (propagate(q, xr, b.x, r->bk, c.s_max, q2, nullptr)) return false;
+  const double dy = q2[0] - b.p[0], dz = q2[1] - b.p[1];
+  if (!(std::fabs(dy) <= c.merge_dy && std::fabs(dz) <= c.merge_dz && std::fabs(q2[2] - b.p[2]) <= c.merge_dsinphi &&
+        std::fabs(q2[3] - b.p[3]) <= c.merge_dtanl && std::fabs(q2[4] - b.p[4]) <= c.merge_dqpt))
+    return false;
+  *score = dy * dy / (b.C[tri(0, 0)] + c.sigma_y * c.sigma_y) + dz * dz / (b.C[tri(1, 1)] + c.sigma_z * c.sigma_z);
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+orc_merge* orc_merge_run(orc_run* r, const int32_t* sector_phys) {
+  orc_merge* m = new orc_merge();
+  const orc_config& c = r->cfg;
+  const uint32_t R = r->R, nt = (uint32_t)r->trk_tracklet.size();
+  std::vector<MergeTrack> T(nt);
+  for (uint32_t k = 0; k < nt; ++k) {
+    const uint32_t i = r->trk_tracklet[k];
+    MergeTrack& t = T[k];
+    t.sector = r->start_row[i] / R;
+    t.phys = sector_phys ? sector_phys[t.sector] : -1;
+    t.x = r->rc[r->tk_xref[i]].X;
+    std::memcpy(t.p, &r->tk_param[(size_t)i * 5], 5 * sizeof(double));
+    std::memcpy(t.C, &r->tk_cov[(size_t)i * 15], 15 * sizeof(double));
+    t.r_in = radius_of(t.x, t.p[0]);
+    t.first = r->trk_first[k];
+    t.n = r->trk_first[k + 1] - r->trk_first[k];
+  }
+  // C8.3 mutual best: each track's best successor and best predecessor
+  std::vector<int32_t> succ(nt, -1), pred(nt, -1);
+  std::vector<double> s_succ(nt, 0.0), s_pred(nt, 0.0);
+  for (uint32_t a = 0; a < nt; ++a) {
+    if (T[a].phys < 0) continue;
+    for (uint32_t b = 0; b < nt; ++b) {
+      if (b == a || T[b].phys < 0) continue;
+      double sc;
+      if (!match_pair(r, T[a], T[b], &sc)) continue;
+      if (succ[a] < 0 || sc < s_succ[a] || (sc == s_succ[a] && (int32_t)b < succ[a])) {
+        succ[a] = (int32_t)b;
+        s_succ[a] = sc;
+      }
+      if (pred[b] < 0 || sc < s_pred[b] || (sc == s_pred[b] && (int32_t)a < pred[b])) {
+        pred[b] = (int32_t)a;
+        s_pred[b] = sc;
+      }
+    }
+  }
+  m->next.assign(nt, -1);
+  m->prev.assign(nt, -1);
+  for (uint32_t a = 0; a < nt; ++a)
+    if (succ[a] >= 0 && pred[succ[a]] == (int32_t)a) {
+      m->next[a] = succ[a];
+      m->prev[succ[a]] = (int32_t)a;
+    }
+  // C9 chains from their heads, refit of chains of two or more segments
+  std::vector<int32_t> pos_of(r->sorted_id.size());
+  for (uint32_t p = 0; p < r->sorted_id.size(); ++p) pos_of[r->sorted_id[p]] = (int32_t)p;
+  m->head.assign(nt, -1);
+  m->first.assign(1, 0);
+  const double vy = c.sigma_y * c.sigma_y, vz = c.sigma_z * c.sigma_z;
+  for (uint32_t h = 0; h < nt; ++h) {
+    if (m->prev[h] >= 0) continue;
+    std::vector<uint32_t> chain;
+    for (int32_t k = (int32_t)h; k >= 0; k = m->next[k]) {
+      chain.push_back((uint32_t)k);
+      m->head[k] = (int32_t)h;
+    }
+    m->heads.push_back(h);
+    m->nseg.push_back((int32_t)chain.size());
+    for (uint32_t k : chain)
+      for (uint32_t j = 0; j < T[k].n; ++j) m->clusters.push_back(r->trk_clusters[T[k].first + j]);
+    m->first.push_back((uint32_t)m->clusters.size());
+    double P[5], Cv[15], chi2 = 0.0;
+    int ndf = 2 * (int)(m->first.back() - m->first[m->first.size() - 2]) - 5;
+    std::memcpy(P, T[h].p, sizeof P);
+    std::memcpy(Cv, T[h].C, sizeof Cv);
+    chi2 = r->tk_chi2[r->trk_tracklet[h]];
+    if (chain.size() > 1) {
+      // the clusters of the chain (each segment's own clusters, ascending row) with row and position
+      struct Hit { uint32_t seg, row; int32_t pos; };
+      std::vector<Hit> hits;
+      for (uint32_t k : chain)
+        for (uint32_t j = 0; j < T[k].n; ++j) {
+          const uint32_t id = r->trk_clusters[T[k].first + j];
+          const uint32_t sr = (uint32_t)(std::upper_bound(r->off.begin(), r->off.end(), id) - r->off.begin()) - 1;
+          hits.push_back(Hit{k, sr % R, pos_of[id]});
+        }
+      // hits are in chain order, ascending row inside a segment; walk them backwards
+      const MergeTrack& last = T[chain.back()];
+      double q[5], x = last.x;
+      std::memcpy(q, last.p, sizeof q);
+      const Hit& ho = hits.back();
+      double q2[5];
+      bool ok = propagate(q, x, r->rc[ho.row].X, r->bk, c.s_max, q2, nullptr) == 0;
+      if (ok) {
+        std::memcpy(q, q2, sizeof q);
+        q[0] = r->sy[ho.pos];
+        q[1] = r->sz[ho.pos];
+        x = r->rc[ho.row].X;
+        Track5 t;
+        std::memcpy(t.p, q, sizeof q);
+        set_c0(c, t.C);
+        chi2 = 0.0;
+        uint32_t seg = ho.seg;
+        for (int k = (int)hits.size() - 2; k >= 0 && ok; --k) {
+          const Hit& hh = hits[k];
+          if (hh.seg != seg) {   // into the previous segment's frame
+            const int dphys = T[hh.seg].phys % 18 - T[seg].phys % 18;
+            int step = dphys;
+            if (step == 17) step = -1;
+            if (step == -17) step = 1;
+            double xr, qr[5], J[5][5];
+            ok = rotate(x, t.p, step * (20.0 * kPi / 180.0), r->bk, &xr, qr, J);
+            if (!ok) break;
+            std::memcpy(t.p, qr, sizeof qr);
+            transport_cov(t.C, J);
+            x = xr;
+            seg = hh.seg;
+          }
+          ok = prop_step(r, t, x, r->rc[hh.row].X);
+          if (!ok) break;
+          x = r->rc[hh.row].X;
+          kf_update(t.p, t.C, r->sy[hh.pos], r->sz[hh.pos], vy, vz, &chi2);
+        }
+        if (ok) {
+          std::memcpy(P, t.p, sizeof P);
+          std::memcpy(Cv, t.C, sizeof Cv);
+        }
+      }
+      if (!ok) ndf = -1;
+    }
+    for (int q = 0; q < 5; ++q) m->param.push_back(P[q]);
+    for (int q = 0; q < 15; ++q) m->cov.push_back(Cv[q]);
+    m->chi2.push_back(chi2);
+    m->ndf.push_back(ndf);
+  }
+  return m;
+}
+
+void orc_merge_destroy(orc_merge* m) { delete m; }
+
+uint64_t orc_merge_get(orc_merge* m, int what, void* dst, uint64_t cap) {
+  const void* src = nullptr;
+  uint64_t bytes = 0;
+  switch (what) {
+#define ORC_MCASE(id, vec)                      \
+  case id:                                      \
+    src = m->vec.data();                        \
+    bytes = m->vec.size() * sizeof(m->vec[0]);  \
+    break;
+    ORC_MCASE(ORC_M_NEXT, next)
+    ORC_MCASE(ORC_M_HEAD, head)
+    ORC_MCASE(ORC_M_HEADS, heads)
+    ORC_MCASE(ORC_M_NSEG, nseg)
+    ORC_MCASE(ORC_M_PARAM, param)
+    ORC_MCASE(ORC_M_COV, cov)
+    ORC_MCASE(ORC_M_CHI2, chi2)
+    ORC_MCASE(ORC_M_NDF, ndf)
+    ORC_MCASE(ORC_M_FIRST, first)
+    ORC_MCASE(ORC_M_CLUSTERS, clusters)
+#undef ORC_MCASE
+    default:
+      return 0;
+  }
+  if (dst && src) std::memcpy(dst, src, std::min(cap, bytes));
+  return bytes;
+}
+
+int orc_rotate(double x, const double* p_in, double d, double bz, double* x_out, double* p_out, double* J) {
+  double Jm[5][5];
+  if (!rotate(x, p_in, d, -kCB * bz, x_out, p_out, Jm)) return 1;
+  if (J)
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) J[i * 5 + j] = Jm[i][j];
+  return 0;
+}
+
 uint64_t orc_get(orc_run* r, int what, void* dst, uint64_t cap) {
   const void* src = nullptr;
   uint64_t bytes = 0;

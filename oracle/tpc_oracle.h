@@ -43,6 +43,8 @@ typedef struct {
   double gate_nsigma, win_cap, edge_margin;
   int32_t max_miss, min_tracklet_hits, min_track_hits;
   double min_owned_frac;
+  /* C8 merger windows: |dy|, |dz| (cm), |d sin phi|, |d tan lambda|, |d q/pT| (1/GeV) */
+  double merge_dy, merge_dz, merge_dsinphi, merge_dtanl, merge_dqpt;
 } orc_config;
 
 typedef struct orc_run orc_run;
@@ -90,7 +92,32 @@ enum {
 /* Copies the array into dst (cap bytes); returns the bytes the array holds. */
 uint64_t orc_get(orc_run* r, int what, void* dst, uint64_t cap);
 
+/* C8 sector merger + C9 refit on the C7 tracks of a run (after orc_run_select).
+ * sector_phys[S]: physical sector (0..17 A side, 18..35 C side) of each of the
+ * run's sectors, or -1 for a sector with no neighbours (independent chunks);
+ * NULL = no sector has neighbours (nothing merges). */
+typedef struct orc_merge orc_merge;
+orc_merge* orc_merge_run(orc_run* r, const int32_t* sector_phys);
+void orc_merge_destroy(orc_merge* m);
+enum {
+  ORC_M_NEXT = 1,        /* i32 [n_tracks] successor track (-1 none) */
+  ORC_M_HEAD,            /* i32 [n_tracks] head of the track's chain */
+  ORC_M_HEADS,           /* u32 [n_merged] chain heads, ascending */
+  ORC_M_NSEG,            /* i32 [n_merged] segments per chain */
+  ORC_M_PARAM,           /* f64 [n_merged*5] refit (chains of >= 2) or C5 result */
+  ORC_M_COV,             /* f64 [n_merged*15] */
+  ORC_M_CHI2,            /* f64 [n_merged] */
+  ORC_M_NDF,             /* i32 [n_merged] 2*nClusters-5, -1 if the refit failed */
+  ORC_M_FIRST,           /* u32 [n_merged+1] */
+  ORC_M_CLUSTERS         /* u32 [...] input ids, chain order, ascending row in a segment */
+};
+uint64_t orc_merge_get(orc_merge* m, int what, void* dst, uint64_t cap);
+
 /* ---- unit-level entry points used by the pins ---- */
+/* Rotation of a state at x into the frame turned by d (radians), same point in
+ * space; J is the 5x5 Jacobian onto the new plane x' = const.  1 if the track
+ * does not move outward in the new frame. */
+int orc_rotate(double x, const double* p_in, double d, double bz, double* x_out, double* p_out, double* J);
 /* Helix transport of p=(y,z,sinphi,tanl,qpt) from x1 to x2; F is 5x5 row-major.
  * Returns 0 on success, 1 if |sinphi| >= s_max at either end. */
 int orc_propagate(const double* p_in, double x1, double x2, double bz, double s_max,

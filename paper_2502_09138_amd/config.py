@@ -39,6 +39,13 @@ class TrackerConfig:
     min_tracklet_hits: int = 10
     min_track_hits: int = 10
     min_owned_frac: float = 0.5
+    # sector merger (C8): windows on the difference between a segment propagated
+    # into the next sector and the segment found there
+    merge_dy: float = 2.0
+    merge_dz: float = 2.0
+    merge_dsinphi: float = 0.05
+    merge_dtanl: float = 0.05
+    merge_dqpt: float = 1.0
 
     def __post_init__(self):
         if self.row_x is None or self.row_half_y is None:

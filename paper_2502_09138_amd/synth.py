@@ -453,6 +453,26 @@ def pp_time_frame(seed, n_orbits, rate_khz=650.0, mean_tracks=12.0, smear=Smeari
                       tracks_per_collision=lambda rng: int(rng.poisson(mean_tracks)))
 
 
+def boundary_crossers(seed=7, n_tracks=60, smear=Smearing(), pt_range=(0.3, 2.0), sectors=(0, 1, 2)):
+    """A-side sectors 0..2 with primaries aimed at the 20 degree edge between sectors 0 and 1
+    (azimuth at r = 160 cm uniform in 20 +- 4 degrees), so that most leave track segments
+    in two neighbouring sectors; the sector merger's workload."""
+    rng = np.random.default_rng(seed)
+    row_x, row_half_y = row_geometry()
+    pt = np.exp(rng.uniform(math.log(pt_range[0]), math.log(pt_range[1]), n_tracks))
+    q = np.where(rng.random(n_tracks) < 0.5, -1.0, 1.0)
+    kap = curvature(q, pt)
+    theta = np.deg2rad(rng.uniform(16.0, 24.0, n_tracks))
+    phi = theta - np.arcsin(np.clip(kap * 160.0 / 2.0, -1, 1))
+    part = _particles(rng, n_tracks, pt, 0.05, 0.9, phi=phi)
+    part["q"] = q
+    sig = _signal_clusters(rng, part, list(sectors), row_x, row_half_y)
+    lo, hi = _physical_z_extent(list(sectors))
+    ev = _assemble(rng, len(sectors), sig, smear, row_x, row_half_y, lo, hi, name=f"boundary_crossers(seed={seed})")
+    ev.particles = part
+    return ev
+
+
 def helix_state_at_row(part, i, alpha, X, bz=BZ_TESLA):
     """True local track state (y, z, sin phi, tan lambda, q/pT) where particle i crosses x_local = X."""
     kap = curvature(part["q"][i], part["pt"][i], bz)
