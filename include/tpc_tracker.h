@@ -83,6 +83,31 @@
  * C7  Output: tracks in ascending startPos (hence by sector); cluster lists are
  *     input ids of the owned hits in ascending row; parameters are the C5
  *     result at x_ref.
+ * C8  Sector merger (tracks of sectors whose physical numbers are given:
+ *     0..17 one side, 18..35 the other, 20 degrees apart, neighbours one step
+ *     apart on the same side).  Rotation of a state at x into the frame
+ *     turned by d, same point in space: x' = x cos d + y sin d, y' = -x sin d
+ *     + y cos d, phi' = phi - d (fail unless cos phi' > 0), z, tan lambda,
+ *     q/pT unchanged; covariance by the first-order Jacobian onto the plane
+ *     x' = const (dy'/dy = cos phi / cos phi', dz'/dy = -tanl sin d / cos
+ *     phi', dsin phi'/dy = -kappa sin d, dsin phi'/dsin phi = cos phi' /
+ *     cos phi).  Track b (sector of a's neighbour) may follow track a if b's
+ *     innermost point lies at a larger radius sqrt(x_ref^2 + y^2) than a's,
+ *     and a's state, rotated into b's frame and propagated to b's x_ref,
+ *     differs from b's by at most merge_dy, merge_dz, merge_dsinphi,
+ *     merge_dtanl, merge_dqpt; score = dy^2/(C_b,yy + sigma_y^2) +
+ *     dz^2/(C_b,zz + sigma_z^2).  Each a keeps its best successor and each b
+ *     its best predecessor (smallest score, ties to the smaller track index);
+ *     a -> b is linked when both agree.  Chains start at tracks without a
+ *     predecessor, in ascending track order.
+ * C9  Refit of a chain of two or more segments: from the outermost cluster of
+ *     its last segment (state: that segment's C5 result propagated there, y
+ *     and z set to the cluster, C = C0) inward over every cluster of the
+ *     chain (each segment's own clusters, descending row), rotating the state
+ *     and covariance into the previous segment's frame where the chain
+ *     crosses a sector edge; result at the innermost cluster of the first
+ *     segment, chi2 of the pass, ndf = 2*nClusters - 5 (-1 if a rotation or
+ *     propagation fails; the chain then keeps its first segment's result).
  *
  * Floating point: C1, C2 and the C6 fraction test are exact float32
  * definitions (bit-identical results expected).  C5 runs in float32 on the
@@ -104,7 +129,7 @@
 extern "C" {
 #endif
 
-#define TPC_ABI_VERSION 1u
+#define TPC_ABI_VERSION 2u
 #define TPC_MAX_ROWS 255
 #define TPC_MAX_ROW_HITS 65535u       /* clusters per (sector, row) */
 #define TPC_MAX_COORD 16384.0f        /* |y|, |z| bound (cm) for exact grid searches */
@@ -148,6 +173,9 @@ typedef struct {
   double gate_nsigma, win_cap, edge_margin;    /* search gate g, window cap (cm), edge margin (cm) */
   int32_t max_miss, min_tracklet_hits, min_track_hits;
   double min_owned_frac;
+  /* C8 merger windows on (segment propagated into the next sector) - (segment found there):
+   * |dy|, |dz| (cm), |d sin phi|, |d tan lambda|, |d q/pT| (1/GeV) */
+  double merge_dy, merge_dz, merge_dsinphi, merge_dtanl, merge_dqpt;
   /* schedule of the tracklet kernel (results are identical):
    * 0 = automatic, 1 = one lane per tracklet with per-lane grid gathers,
    * 2 = row-synchronous waves with the row grid staged in LDS */
@@ -262,6 +290,35 @@ tpc_status tpc_get_tracks(tpc_tracker* t, uint64_t request_id, int32_t blocking,
  * come from the completed request).  Valid until tpc_release or destroy; read
  * them on the tracker's stream or after the call returns. */
 tpc_status tpc_get_tracks_device(tpc_tracker* t, uint64_t request_id, int32_t blocking, tpc_tracks* out);
+
+/* C8 + C9 on the tracks of a completed request (before its release): links
+ * track segments across the edges between neighbouring sectors and refits the
+ * merged chains.  sector_phys: HOST [n_sectors of the request], the physical
+ * sector number (0..35) of each of the frame's sectors, -1 for a sector with
+ * no neighbours (an independent chunk); NULL = none has neighbours.  Runs on
+ * the tracker's stream and waits for it; *out receives views of tracker-owned
+ * host memory, valid until tpc_release or destroy: per input track its
+ * successor (-1) and chain head, per chain (in ascending head order) the head
+ * track, segment count, merged cluster list (input ids: the segments' lists in
+ * chain order) and the refit state at the innermost cluster (a single
+ * segment's chain: its C5 result).  TPC_E_INVAL for an unknown request or a
+ * sector number out of range; TPC_E_CAPACITY if the request had failed. */
+typedef struct {
+  uint32_t n_tracks;               /* tracks of the request */
+  uint32_t n_chains;
+  uint64_t n_chain_clusters;
+  const int32_t* next;             /* [n_tracks] */
+  const uint32_t* head_of;         /* [n_tracks] */
+  const uint32_t* heads;           /* [n_chains] */
+  const int32_t* nseg;             /* [n_chains] */
+  const uint32_t* first;           /* [n_chains+1] offsets into clusters */
+  const uint32_t* clusters;        /* [n_chain_clusters] input ids */
+  const float* param;              /* [n_chains*5] y, z, sin phi, tan lambda, q/pT at the head's x_ref */
+  const float* cov;                /* [n_chains*15] */
+  const float* chi2;               /* [n_chains] */
+  const int32_t* ndf;              /* [n_chains] */
+} tpc_merged;
+tpc_status tpc_merge_sectors(tpc_tracker* t, uint64_t request_id, const int32_t* sector_phys, tpc_merged* out);
 
 /* Waits for the request and frees its slot. */
 tpc_status tpc_release(tpc_tracker* t, uint64_t request_id);

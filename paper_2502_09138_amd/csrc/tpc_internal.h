@@ -115,6 +115,34 @@ struct DevPtrs {
   uint64_t max_track_clusters;
 };
 
+// C8/C9 sector merger on the tracks of a completed request (all in the workspace).
+struct MergeArgs {
+  const int32_t* phys;                 // [S] physical sector of each of the frame's sectors, -1: no neighbours
+  int32_t* nbr;                        // [2S] frame sector of the -1 / +1 neighbour, -1 if absent
+  uint32_t* sec_first;                 // [S+1] first track of each sector
+  int32_t* succ;                       // [MT] best successor
+  unsigned long long* pred_key;        // [MT] (score bits << 32) | best predecessor
+  int32_t* next;                       // [MT] linked successor, -1 none
+  uint32_t* has_pred;                  // [MT]
+  uint32_t* head_flag;                 // [MT]
+  uint32_t* head_scan;                 // [MT+1] chain index of each head
+  uint32_t* chain_clusters;            // [MT] clusters of the chain (at heads)
+  uint32_t* cl_scan;                   // [MT+1]
+  uint32_t* heads;                     // [MT] per chain: head track
+  uint32_t* head_of;                   // [MT] per track: its chain's head
+  uint32_t* first;                     // [MT+1] per chain: first merged cluster
+  uint32_t* clusters;                  // [MC] merged cluster lists
+  float* param;                        // [5 MT] per chain, track-major
+  float* cov;                          // [15 MT]
+  float* chi2;                         // [MT]
+  int32_t* ndf;                        // [MT] -1: refit failed
+  int32_t* nseg;                       // [MT]
+  double cos20, sin20;                 // the rotation between neighbouring sectors
+  double bk, s_max;                    // -c_B * Bz and the |sin phi| limit, in double
+  double vy, vz, c0_sinphi, c0_tanl, c0_qpt;   // measurement and initial variances, in double
+  double dy, dz, dsinphi, dtanl, dqpt; // C8 windows
+};
+
 constexpr int kScanBlock = 1024;                   // elements per scan block (256 threads x 4)
 constexpr int kScanMaxBlocks = 8192;               // supports scans of up to 8M elements
 
@@ -124,6 +152,7 @@ void launch_links(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
 void launch_clean_starts(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
 void launch_tracklets(const DevPtrs& d, const KfConst& k, uint32_t max_row_hits, hipStream_t s);
 void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipStream_t s);
+void launch_merge(const DevPtrs& d, const MergeArgs& m, const KfConst& k, uint32_t n_tracks, hipStream_t s);
 // exclusive scans; n read from *n_dev when n_dev != nullptr (then n_max bounds the grid)
 void launch_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, unsigned long long* blocks, hipStream_t s);
 void launch_scan_u64(const unsigned long long* in, unsigned long long* out, const uint32_t* n_dev, uint32_t n_max,

@@ -55,7 +55,8 @@ struct Layout {   // byte offsets of every workspace buffer
       row_start_off, start_pos, start_sr, wave_off, tile_off, tile_sr, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, W, own_part, tk_pack,
       tk_scan, acc_list,
       out_sector, out_start, out_first, out_clusters, out_xref, out_param, out_cov, out_chi2, out_ndf, scan_blocks,
-      hdr, in_y, in_z, total;
+      hdr, in_y, in_z, m_phys, m_nbr, m_sec_first, m_succ, m_pred_key, m_next, m_has_pred, m_head_flag, m_head_scan,
+      m_chain_cl, m_cl_scan, m_heads, m_head_of, m_first, m_clusters, m_param, m_cov, m_chi2, m_ndf, m_nseg, total;
 };
 
 struct Caps {
@@ -128,6 +129,27 @@ Layout layout_of(const Caps& k) {
   L.hdr = take(sizeof(ResultHeader));
   L.in_y = take(k.N * 4);
   L.in_z = take(k.N * 4);
+  // C8/C9 sector merger
+  L.m_phys = take((uint64_t)k.Smax * 4);
+  L.m_nbr = take((uint64_t)k.Smax * 8);
+  L.m_sec_first = take(((uint64_t)k.Smax + 1) * 4);
+  L.m_succ = take(k.MT * 4);
+  L.m_pred_key = take(k.MT * 8);
+  L.m_next = take(k.MT * 4);
+  L.m_has_pred = take(k.MT * 4);
+  L.m_head_flag = take(k.MT * 4);
+  L.m_head_scan = take((k.MT + 1) * 4);
+  L.m_chain_cl = take(k.MT * 4);
+  L.m_cl_scan = take((k.MT + 1) * 4);
+  L.m_heads = take(k.MT * 4);
+  L.m_head_of = take(k.MT * 4);
+  L.m_first = take((k.MT + 1) * 4);
+  L.m_clusters = take(k.MC * 4);
+  L.m_param = take(5 * k.MT * 4);
+  L.m_cov = take(15 * k.MT * 4);
+  L.m_chi2 = take(k.MT * 4);
+  L.m_ndf = take(k.MT * 4);
+  L.m_nseg = take(k.MT * 4);
   L.total = o;
   return L;
 }
@@ -149,6 +171,9 @@ std::string validate_config(const tpc_tracker_config* c) {
   if (!(c->gate_nsigma > 0.0) || !(c->win_cap > 0.0) || !(c->seed_qpt_max > 0.0)) return "gate/cap/qpt_max must be > 0";
   if (!(c->c0_sinphi > 0.0 && c->c0_tanl > 0.0 && c->c0_qpt > 0.0)) return "initial variances must be > 0";
   if (c->max_miss < 0 || c->min_tracklet_hits < 3 || c->min_track_hits < 1) return "hit-count cuts out of range";
+  if (!(c->merge_dy >= 0.0 && c->merge_dz >= 0.0 && c->merge_dsinphi >= 0.0 && c->merge_dtanl >= 0.0 &&
+        c->merge_dqpt >= 0.0))
+    return "merge windows must be >= 0";
   if (c->max_sectors < 1) return "max_sectors must be >= 1";
   if (c->tracklet_schedule < 0 || c->tracklet_schedule > 2) return "tracklet_schedule must be 0, 1 or 2";
   if (c->max_clusters >= (1ull << 31)) return "max_clusters must be < 2^31";
@@ -204,6 +229,9 @@ struct tpc_tracker {
   SectorConst* h_secs = nullptr;
   ResultHeader* h_hdr = nullptr;
   char* h_out = nullptr;      // all outputs, laid out like the device outputs
+  char* h_merge = nullptr;    // merger outputs (allocated at the first merge), laid out like the device ones
+  int32_t* h_phys = nullptr;  // pinned copy of the sector numbers of a merge
+  tpc_merged merged{};
   hipEvent_t done = nullptr;
   hipEvent_t ev[kPasses + 1] = {};
   uint32_t timing = 0;   // mask of timed passes
@@ -313,6 +341,11 @@ void tpc_default_config(tpc_tracker_config* c) {
   c->min_tracklet_hits = 10;
   c->min_track_hits = 10;
   c->min_owned_frac = 0.5;
+  c->merge_dy = 2.0;
+  c->merge_dz = 2.0;
+  c->merge_dsinphi = 0.05;
+  c->merge_dtanl = 0.05;
+  c->merge_dqpt = 1.0;
   c->max_sectors = 36;
   c->max_clusters = 2000000;
   c->device = 0;
@@ -448,6 +481,8 @@ void tpc_tracker_destroy(tpc_tracker* t) {
   if (t->h_hdr) (void)hipHostFree(t->h_hdr);
   if (t->h_out) (void)hipHostFree(t->h_out);
   if (t->h_rows) (void)hipHostFree(t->h_rows);
+  if (t->h_merge) (void)hipHostFree(t->h_merge);
+  if (t->h_phys) (void)hipHostFree(t->h_phys);
   if (t->own_stream && t->stream) (void)hipStreamDestroy(t->stream);
   delete t;
 }
@@ -769,6 +804,110 @@ tpc_status tpc_get_tracks_device(tpc_tracker* t, uint64_t request_id, int32_t bl
   out->cov = d.out_cov;
   out->chi2 = d.out_chi2;
   out->ndf = d.out_ndf;
+  return TPC_OK;
+}
+
+tpc_status tpc_merge_sectors(tpc_tracker* t, uint64_t request_id, const int32_t* sector_phys, tpc_merged* out) {
+  if (!t || !out) return fail(TPC_E_INVAL, "NULL argument");
+  if (!t->in_flight || request_id != t->cur_id) return fail(TPC_E_INVAL, "unknown request id");
+  const uint32_t S = t->cur_S;
+  if (sector_phys)
+    for (uint32_t s = 0; s < S; ++s)
+      if (sector_phys[s] < -1 || sector_phys[s] >= 36) return fail(TPC_E_INVAL, "sector number out of range [-1, 35]");
+  HIP_TRY(hipSetDevice(t->device));
+  HIP_TRY(hipEventSynchronize(t->done));
+  const ResultHeader h = *t->h_hdr;
+  if (h.error_flags) return fail(h.error_flags & TPC_ERR_NONFINITE ? TPC_E_INPUT : TPC_E_CAPACITY, "the request failed");
+  const Layout& L = t->lay;
+  const Caps& hc = t->host_caps;
+  const Layout HL = layout_of(hc);   // pinned merge buffers are laid out for the create-time capacities
+  if (!t->h_merge) {
+    if (hipHostMalloc((void**)&t->h_merge, HL.m_nseg + hc.MT * 4 - HL.m_next) != hipSuccess ||
+        hipHostMalloc((void**)&t->h_phys, (size_t)hc.Smax * 4) != hipSuccess)
+      return fail(TPC_E_NOMEM, "hipHostMalloc merge buffers");
+  }
+  char* w = t->ws;
+  MergeArgs m{};
+  m.phys = (const int32_t*)(w + L.m_phys);
+  m.nbr = (int32_t*)(w + L.m_nbr);
+  m.sec_first = (uint32_t*)(w + L.m_sec_first);
+  m.succ = (int32_t*)(w + L.m_succ);
+  m.pred_key = (unsigned long long*)(w + L.m_pred_key);
+  m.next = (int32_t*)(w + L.m_next);
+  m.has_pred = (uint32_t*)(w + L.m_has_pred);
+  m.head_flag = (uint32_t*)(w + L.m_head_flag);
+  m.head_scan = (uint32_t*)(w + L.m_head_scan);
+  m.chain_clusters = (uint32_t*)(w + L.m_chain_cl);
+  m.cl_scan = (uint32_t*)(w + L.m_cl_scan);
+  m.heads = (uint32_t*)(w + L.m_heads);
+  m.head_of = (uint32_t*)(w + L.m_head_of);
+  m.first = (uint32_t*)(w + L.m_first);
+  m.clusters = (uint32_t*)(w + L.m_clusters);
+  m.param = (float*)(w + L.m_param);
+  m.cov = (float*)(w + L.m_cov);
+  m.chi2 = (float*)(w + L.m_chi2);
+  m.ndf = (int32_t*)(w + L.m_ndf);
+  m.nseg = (int32_t*)(w + L.m_nseg);
+  m.cos20 = std::cos(20.0 * 3.14159265358979323846 / 180.0);
+  m.sin20 = std::sin(20.0 * 3.14159265358979323846 / 180.0);
+  const tpc_tracker_config& c = t->cfg;
+  m.bk = -kCB * c.bz_tesla;
+  m.s_max = c.s_max;
+  m.vy = c.sigma_y * c.sigma_y;
+  m.vz = c.sigma_z * c.sigma_z;
+  m.c0_sinphi = c.c0_sinphi;
+  m.c0_tanl = c.c0_tanl;
+  m.c0_qpt = c.c0_qpt;
+  m.dy = c.merge_dy;
+  m.dz = c.merge_dz;
+  m.dsinphi = c.merge_dsinphi;
+  m.dtanl = c.merge_dtanl;
+  m.dqpt = c.merge_dqpt;
+  for (uint32_t s = 0; s < S; ++s) t->h_phys[s] = sector_phys ? sector_phys[s] : -1;
+  hipStream_t st = t->stream;
+  HIP_TRY(hipMemcpyAsync((void*)m.phys, t->h_phys, (size_t)S * 4, hipMemcpyHostToDevice, st));
+  const uint32_t n = h.n_tracks;
+  launch_merge(t->d, m, t->kc, n, st);
+  HIP_TRY(hipGetLastError());
+  // counts, then the arrays
+  uint32_t* cnt = (uint32_t*)(t->h_merge + (HL.m_head_scan - HL.m_next));
+  HIP_TRY(hipMemcpyAsync(cnt, m.head_scan + n, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(cnt + 1, m.cl_scan + n, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const uint32_t nc = n ? cnt[0] : 0;
+  const uint64_t ncl = n ? cnt[1] : 0;
+  auto host = [&](uint64_t off) { return t->h_merge + (off - HL.m_next); };
+  struct {
+    const void* src;
+    uint64_t off, bytes;
+  } cp[] = {
+      {m.next, HL.m_next, n * 4ull},           {m.head_of, HL.m_head_of, n * 4ull},
+      {m.heads, HL.m_heads, nc * 4ull},        {m.nseg, HL.m_nseg, nc * 4ull},
+      {m.first, HL.m_first, (nc + 1) * 4ull},  {m.clusters, HL.m_clusters, ncl * 4},
+      {m.param, HL.m_param, nc * 20ull},       {m.cov, HL.m_cov, nc * 60ull},
+      {m.chi2, HL.m_chi2, nc * 4ull},          {m.ndf, HL.m_ndf, nc * 4ull},
+  };
+  if (n) {
+    for (auto& e : cp)
+      if (e.bytes) HIP_TRY(hipMemcpyAsync(host(e.off), e.src, e.bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  } else {
+    *(uint32_t*)host(HL.m_first) = 0;
+  }
+  std::memset(out, 0, sizeof *out);
+  out->n_tracks = n;
+  out->n_chains = nc;
+  out->n_chain_clusters = ncl;
+  out->next = (const int32_t*)host(HL.m_next);
+  out->head_of = (const uint32_t*)host(HL.m_head_of);
+  out->heads = (const uint32_t*)host(HL.m_heads);
+  out->nseg = (const int32_t*)host(HL.m_nseg);
+  out->first = (const uint32_t*)host(HL.m_first);
+  out->clusters = (const uint32_t*)host(HL.m_clusters);
+  out->param = (const float*)host(HL.m_param);
+  out->cov = (const float*)host(HL.m_cov);
+  out->chi2 = (const float*)host(HL.m_chi2);
+  out->ndf = (const int32_t*)host(HL.m_ndf);
   return TPC_OK;
 }
 

@@ -19,7 +19,7 @@ from .config import TrackerConfig
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtpc_tracker.so")
 
-TPC_ABI_VERSION = 1
+TPC_ABI_VERSION = 2
 TPC_OK, TPC_E_INVAL, TPC_E_NOMEM, TPC_E_DEVICE, TPC_E_CAPACITY, TPC_E_NOTREADY, TPC_E_INPUT, TPC_E_BUSY = \
     0, -1, -2, -3, -4, -5, -6, -7
 TPC_IN_DEVICE, TPC_IN_HOST = 0, 1
@@ -50,6 +50,8 @@ class _Config(C.Structure):
         ("gate_nsigma", C.c_double), ("win_cap", C.c_double), ("edge_margin", C.c_double),
         ("max_miss", C.c_int32), ("min_tracklet_hits", C.c_int32), ("min_track_hits", C.c_int32),
         ("min_owned_frac", C.c_double),
+        ("merge_dy", C.c_double), ("merge_dz", C.c_double), ("merge_dsinphi", C.c_double),
+        ("merge_dtanl", C.c_double), ("merge_dqpt", C.c_double),
         ("tracklet_schedule", C.c_int32),
         ("max_sectors", C.c_uint32), ("max_clusters", C.c_uint64), ("max_tracklets", C.c_uint64),
         ("max_tracks", C.c_uint64), ("max_track_clusters", C.c_uint64),
@@ -77,10 +79,20 @@ class _Tracks(C.Structure):
     ]
 
 
+class _Merged(C.Structure):
+    _fields_ = [
+        ("n_tracks", C.c_uint32), ("n_chains", C.c_uint32), ("n_chain_clusters", C.c_uint64),
+        ("next", C.POINTER(C.c_int32)), ("head_of", C.POINTER(C.c_uint32)), ("heads", C.POINTER(C.c_uint32)),
+        ("nseg", C.POINTER(C.c_int32)), ("first", C.POINTER(C.c_uint32)), ("clusters", C.POINTER(C.c_uint32)),
+        ("param", C.POINTER(C.c_float)), ("cov", C.POINTER(C.c_float)), ("chi2", C.POINTER(C.c_float)),
+        ("ndf", C.POINTER(C.c_int32)),
+    ]
+
+
 EXPORTED = ("tpc_default_config", "tpc_workspace_bytes", "tpc_tracker_create", "tpc_tracker_destroy",
             "tpc_workspace_bytes_for", "tpc_tracker_bind_workspace", "tpc_track_timeframe_scratch",
             "tpc_track_timeframe", "tpc_get_tracks", "tpc_get_tracks_device", "tpc_release", "tpc_last_error", "tpc_debug_copy",
-            "tpc_set_timing", "tpc_get_pass_times", "tpc_set_tracklet_schedule")
+            "tpc_set_timing", "tpc_get_pass_times", "tpc_set_tracklet_schedule", "tpc_merge_sectors")
 
 _lib = None
 
@@ -113,6 +125,8 @@ def load():
     L.tpc_get_tracks.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, P(_Tracks)]
     L.tpc_get_tracks_device.restype = C.c_int32
     L.tpc_get_tracks_device.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, P(_Tracks)]
+    L.tpc_merge_sectors.restype = C.c_int32
+    L.tpc_merge_sectors.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, P(_Merged)]
     L.tpc_release.restype = C.c_int32
     L.tpc_release.argtypes = [C.c_void_p, C.c_uint64]
     L.tpc_last_error.restype = C.c_char_p
@@ -146,7 +160,8 @@ def make_config(cfg: TrackerConfig, *, max_clusters, max_sectors=36, max_trackle
     c.bz_tesla = cfg.bz
     for f in ("sigma_y", "sigma_z", "grid_hits_per_bin", "win_a_y", "win_b_y", "win_a_z", "win_b_z", "link_nsigma",
               "s_max", "seed_qpt_max", "c0_sinphi", "c0_tanl", "c0_qpt", "gate_nsigma", "win_cap", "edge_margin",
-              "max_miss", "min_tracklet_hits", "min_track_hits", "min_owned_frac"):
+              "max_miss", "min_tracklet_hits", "min_track_hits", "min_owned_frac", "merge_dy", "merge_dz",
+              "merge_dsinphi", "merge_dtanl", "merge_dqpt"):
         setattr(c, f, getattr(cfg, f))
     c.max_sectors = max_sectors
     c.max_clusters = max_clusters
@@ -298,6 +313,34 @@ class Tracker:
         _check(load().tpc_get_tracks(self._h, rid, 1, C.byref(t)))
         return dict(n_tracks=t.n_tracks, n_track_clusters=t.n_track_clusters, n_tracklets=t.n_tracklets,
                     n_steps=t.n_steps, error_flags=t.error_flags)
+
+    def merge(self, rid, sector_phys=None):
+        """C8 + C9 on the tracks of completed request rid (before release); sector_phys[s] = physical
+        sector 0..35 of the frame's sector s (-1 or None: no neighbours).  Returns a dict of arrays."""
+        sp = None if sector_phys is None else np.ascontiguousarray(sector_phys, np.int32)
+        m = _Merged()
+        _check(load().tpc_merge_sectors(self._h, rid, None if sp is None else sp.ctypes.data, C.byref(m)))
+        n, nc, ncl = m.n_tracks, m.n_chains, m.n_chain_clusters
+
+        def arr(ptr, count, dt):
+            if count == 0:
+                return np.zeros(0, dt)
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=True)
+
+        return dict(next=arr(m.next, n, np.int32), head_of=arr(m.head_of, n, np.uint32),
+                    heads=arr(m.heads, nc, np.uint32), nseg=arr(m.nseg, nc, np.int32),
+                    first=arr(m.first, nc + 1, np.uint32), clusters=arr(m.clusters, ncl, np.uint32),
+                    param=arr(m.param, 5 * nc, np.float32).reshape(nc, 5),
+                    cov=arr(m.cov, 15 * nc, np.float32).reshape(nc, 15), chi2=arr(m.chi2, nc, np.float32),
+                    ndf=arr(m.ndf, nc, np.int32))
+
+    def track_and_merge(self, y, z, row_offsets, z_lo, z_hi, sector_phys, *, host=False):
+        """One frame through C1..C9: (tracks, merged chains)."""
+        rid = self.submit(y, z, row_offsets, z_lo, z_hi, host=host)
+        try:
+            return self.get(rid), self.merge(rid, sector_phys)
+        finally:
+            self.release(rid)
 
     def release(self, rid):
         _check(load().tpc_release(self._h, rid))

@@ -43,7 +43,8 @@ def test_defaults_match_python_config(lib):
     assert c.bz_tesla == py.bz
     for f in ("sigma_y", "sigma_z", "grid_hits_per_bin", "win_a_y", "win_b_y", "win_a_z", "win_b_z", "link_nsigma",
               "s_max", "seed_qpt_max", "c0_sinphi", "c0_tanl", "c0_qpt", "gate_nsigma", "win_cap", "edge_margin",
-              "max_miss", "min_tracklet_hits", "min_track_hits", "min_owned_frac"):
+              "max_miss", "min_tracklet_hits", "min_track_hits", "min_owned_frac", "merge_dy", "merge_dz",
+              "merge_dsinphi", "merge_dtanl", "merge_dqpt"):
         assert getattr(c, f) == getattr(py, f), f
 
 
