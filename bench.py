@@ -36,32 +36,42 @@ K1_BYTES_PER_CLUSTER = 22.0     # read y, z; write sorted (y, z), id, ~2 B of bi
 K2_BYTES_PER_CLUSTER = 18.0     # read own (y, z) + each adjacent row once + bin starts; write up0/down0
 
 
-# HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scaled on a 1 GiB device copy) from two
-# rocprofv3 --pmc passes of this script (commands and tables in profiles/), valid for the kernel sources
-# with these SHA-1 digests; reported as null once a source differs.
-PMC_SOURCES = {
-    "paper_2502_09138_amd/csrc/tracklet.hip": "04da676727566285dd7ca194c22faebfb6e4efa5",
-    "paper_2502_09138_amd/csrc/links.hip": "ad6bcd87cc9f7c3f0839ae36deca241dbd83786b",
-    "paper_2502_09138_amd/csrc/grid.hip": "6460655febd2a7f572bd7741e338bdc971bf3f8e",
-    "paper_2502_09138_amd/csrc/device_common.h": "b4b103e57db5db269528a9bdae40217f2bb52ff1",
-    "paper_2502_09138_amd/csrc/tpc_internal.h": "c30ec36732874be540b4abaaf919120a340376b4",
+# Stored rocprofv3 figures per workload (commands and tables in profiles/): HBM bytes per launch
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, scaled on a 1 GiB device copy) and VALU wave
+# instructions per launch (SQ_INSTS_VALU).  They hold for the kernel sources with the listed SHA-1
+# digests and are reported as null once a source differs; they are not measured in this run.
+PROFILE_SOURCES = (
+    "paper_2502_09138_amd/csrc/tracklet.hip",
+    "paper_2502_09138_amd/csrc/links.hip",
+    "paper_2502_09138_amd/csrc/grid.hip",
+    "paper_2502_09138_amd/csrc/device_common.h",
+    "paper_2502_09138_amd/csrc/tpc_internal.h",
+)
+PROFILES = {
+    "time_frame": {
+        "digests": ("50dafa9f555f13db346fcd08ad6666c75f4724bb", "ad6bcd87cc9f7c3f0839ae36deca241dbd83786b",
+                    "8d4ffb5e64cc1810222dbe0c811aa511ffde5df6", "b4b103e57db5db269528a9bdae40217f2bb52ff1",
+                    "870a84e59816aedf636e9f025635fcac579f612b"),
+        "traffic_bytes": {"tracklets": 7_540_940_000, "grid": 294_780_000, "neighbours": 473_960_000},
+        "valu_insts": {"tracklets": 1_239_969_573, "grid": 19_770_947, "neighbours": 310_520_732},
+        "files": "profiles/time_frame_hbm_traffic.md, profiles/time_frame_sq_counters.md",
+    },
 }
-MIB = float(1 << 20)
-PMC_TRAFFIC = {   # workload -> pass -> (fetch MiB, write MiB) per launch
-    "central_event": {"tracklets": (65.42, 89.77), "grid": (11.69, 18.10), "neighbours": (40.79, 10.98)},
-    "time_frame": {"tracklets": (7256.53, 1852.76), "grid": (85.07, 135.93), "neighbours": (367.63, 84.48)},
-    "uneven_chunks": {"tracklets": (11965.04, 5476.65), "grid": (166.74, 260.15), "neighbours": (828.96, 158.48)},
-}
+# Issue ceiling of vector instructions: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD every
+# 4 cycles (16 lanes), at 2.4 GHz.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def pmc_traffic(workload, pass_name):
+def stored_profile(workload):
     import hashlib
-    for rel, digest in PMC_SOURCES.items():
+    prof = PROFILES.get(workload)
+    if prof is None:
+        return None
+    for rel, digest in zip(PROFILE_SOURCES, prof["digests"]):
         with open(os.path.join(ROOT, rel), "rb") as f:
             if hashlib.sha1(f.read()).hexdigest() != digest:
                 return None
-    fw = PMC_TRAFFIC.get(workload, {}).get(pass_name)
-    return None if fw is None else round((fw[0] + fw[1]) * MIB)
+    return prof
 
 
 def host_cpu():
@@ -366,24 +376,39 @@ def main():
     value = N * args.steps / elapsed
     pass_ms = {k: float(np.mean(v)) for k, v in bd_acc.items()}
     pass_ms[dominant] = dom_ms   # the dominant pass as timed inside the timed loop
-    k5_bytes = K5_BYTES_PER_STEP * counts["n_steps"] + K5_BYTES_PER_TRACKLET * counts["n_tracklets"]
-    k5_gbs = k5_bytes / (pass_ms["tracklets"] * 1e-3) / 1e9
-    k1_gbs = K1_BYTES_PER_CLUSTER * N / (pass_ms["grid"] * 1e-3) / 1e9
-    k2_gbs = K2_BYTES_PER_CLUSTER * N / (pass_ms["neighbours"] * 1e-3) / 1e9
     k5_name = "k_tracklets_rs (K5, C5)" if tr_schedule_rowsync(args.schedule, ev) else "k_tracklets (K5, C5)"
+    prof = stored_profile(wl["workload"])
+
+    def roof_entry(kernel, pass_name, alg_bytes, issue_bound):
+        ms = pass_ms[pass_name]
+        gbs = alg_bytes / (ms * 1e-3) / 1e9
+        hbm = dict(achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5),
+                   algorithmic_bytes=round(alg_bytes))
+        e = dict(kernel=kernel, kernel_ms=round(ms, 4))
+        traffic = None if prof is None else prof["traffic_bytes"][pass_name]
+        valu = None if prof is None else prof["valu_insts"][pass_name]
+        issue = None if valu is None else valu / (ms * 1e-3) / 1e9
+        if issue_bound and issue is not None:
+            # limited by vector-instruction issue along dependent steps: the roofline is the issue rate
+            e.update(bound="alu", achieved=round(issue, 2), peak=round(VALU_ISSUE_PEAK / 1e9, 1),
+                     unit="G VALU wave-instructions/s", frac=round(issue * 1e9 / VALU_ISSUE_PEAK, 5),
+                     traffic=traffic, hbm=hbm)
+        else:
+            e.update(bound="hbm", traffic=traffic, **hbm)
+            if issue is not None:
+                e["valu_issue_frac"] = round(issue * 1e9 / VALU_ISSUE_PEAK, 5)
+        e["profile"] = (f"traffic and VALU counts from stored rocprofv3 runs ({prof['files']})" if prof is not None
+                        else "no stored rocprofv3 profile for these kernel sources and workload: traffic null")
+        return e
+
+    k5_bytes = K5_BYTES_PER_STEP * counts["n_steps"] + K5_BYTES_PER_TRACKLET * counts["n_tracklets"]
     roof = {
-        "tracklets": dict(kernel=k5_name, bound="hbm", achieved=round(k5_gbs, 2), peak=HBM_PEAK_GBS,
-                          unit="GB/s", frac=round(k5_gbs / HBM_PEAK_GBS, 5), traffic=pmc_traffic(wl["workload"], "tracklets"),
-                          algorithmic_bytes=round(k5_bytes), kernel_ms=round(pass_ms["tracklets"], 4),
-                          note="bound by instruction issue along dependent row steps, not bytes; bytes = 30 B/row step + 700 B/tracklet"),
-        "grid": dict(kernel="k_grid_lds (K1, C1)", bound="hbm", achieved=round(k1_gbs, 2), peak=HBM_PEAK_GBS,
-                     unit="GB/s", frac=round(k1_gbs / HBM_PEAK_GBS, 5), traffic=pmc_traffic(wl["workload"], "grid"),
-                     algorithmic_bytes=round(K1_BYTES_PER_CLUSTER * N), kernel_ms=round(pass_ms["grid"], 4)),
-        "neighbours": dict(kernel="k_links (K2, C2)", bound="hbm", achieved=round(k2_gbs, 2), peak=HBM_PEAK_GBS,
-                           unit="GB/s", frac=round(k2_gbs / HBM_PEAK_GBS, 5),
-                           traffic=pmc_traffic(wl["workload"], "neighbours"),
-                           algorithmic_bytes=round(K2_BYTES_PER_CLUSTER * N), kernel_ms=round(pass_ms["neighbours"], 4)),
+        "tracklets": roof_entry(k5_name, "tracklets", k5_bytes, True),
+        "grid": roof_entry("k_grid_lds (K1, C1)", "grid", K1_BYTES_PER_CLUSTER * N, False),
+        "neighbours": roof_entry("k_links (K2, C2)", "neighbours", K2_BYTES_PER_CLUSTER * N, False),
     }
+    roof["tracklets"]["note"] = ("Kalman steps of one tracklet depend on each other: the kernel is limited by "
+                                 "instruction issue and latency, not bytes; bytes = 30 B/row step + 700 B/tracklet")
     rec = {
         "metric": "TPC clusters/sec tracked at 1 GPU + p50/p99 time-frame latency vs plain path",
         "value": round(value, 1),
