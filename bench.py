@@ -376,7 +376,7 @@ def main():
     value = N * args.steps / elapsed
     pass_ms = {k: float(np.mean(v)) for k, v in bd_acc.items()}
     pass_ms[dominant] = dom_ms   # the dominant pass as timed inside the timed loop
-    k5_name = "k_tracklets_rs (K5, C5)" if tr_schedule_rowsync(args.schedule, ev) else "k_tracklets (K5, C5)"
+    k5_name = "k_tracklets_rs (K5, C5)" if tr_schedule_rowsync(args.schedule, ev) else "k_seed + k_fit (K5, C5)"
     prof = stored_profile(wl["workload"])
 
     def roof_entry(kernel, pass_name, alg_bytes, issue_bound):

@@ -84,6 +84,8 @@ struct DevPtrs {
   float* tk_param;           // [5 * Tcap]
   float* tk_cov;             // [15 * Tcap]
   float* tk_chi2;            // [Tcap]
+  uint32_t* k5_off;          // [SR+1] lane-per-tracklet K5: refit bucket offsets (sector, outermost row)
+  uint32_t* k5_perm;         // [Tcap] tracklets in bucket order
   // C6
   uint32_t* W;               // [N] ownership word (32-bit key) per sorted position
   uint8_t* own_part;         // [R * Tcap] owned hits of a tracklet per selector tile (then prefixes)

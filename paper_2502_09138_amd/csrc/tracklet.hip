@@ -28,6 +28,8 @@
 // the state's z relative to its start hit (zref); z_m - zref is exact in
 // float32 for the hits of one track (Sterbenz), and zref is added back only
 // when the result is stored.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace tpc {
@@ -428,6 +430,7 @@ __device__ __forceinline__ void spd_guard(float* c) {
     }
 }
 
+template <bool kGuard>
 __device__ __forceinline__ void store_tracklet(const DevPtrs& d, uint32_t i, int nh, uint32_t rin, uint32_t rout,
                                                uint32_t r0, const Snap& snap, float chi2, float zref) {
   const uint32_t T = d.tcap;
@@ -440,35 +443,78 @@ __device__ __forceinline__ void store_tracklet(const DevPtrs& d, uint32_t i, int
   float c[15];
 #pragma unroll
   for (int q = 0; q < 15; ++q) c[q] = snap.c[q];
-  spd_guard(c);
+  if (kGuard) spd_guard(c);
 #pragma unroll
   for (int q = 0; q < 15; ++q) d.tk_cov[(size_t)q * T + i] = c[q];
   d.tk_chi2[i] = chi2;
 }
 
+// The covariance guard over every stored tracklet, one lane each (for k_down,
+// whose lanes store as they finish: there the guard would cost the whole wave
+// once for every group of lanes that finish together).
+__global__ void __launch_bounds__(256) k_guard(DevPtrs d) {
+  const uint32_t nt = min(d.hdr->n_starts, d.tcap), T = d.tcap;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
+    if (d.tk_info[i] < 1) continue;
+    float c[15];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) c[q] = d.tk_cov[(size_t)q * T + i];
+    spd_guard(c);
+#pragma unroll
+    for (int q = 0; q < 15; ++q) d.tk_cov[(size_t)q * T + i] = c[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lane-per-tracklet schedule: k_seed, k_up, k_sort, k_down, k_guard.
+//
+// A wave steps as long as its longest lane.  With one loop per pass (chain
+// fit, outward extension, inward refit) a wave steps through its longest
+// chain fit, then its longest extension, then its longest refit, and on a
+// 32-orbit frame only about 56% of the lane steps do work.  Here the chain
+// fit and the outward extension run as one loop (both move outward one row
+// per step, so the lanes of a wave, which hold consecutive tracklets of one
+// sector and start rows close together, stay on the same rows), and the
+// inward refits are regrouped by (sector, outermost row) before they run: a
+// wave's lanes then start the refit on the same row and walk the same rows in
+// step, and most of them stop within a few rows of each other.
+//
+// k_seed: one lane per tracklet walks its chain (dependent up1 gathers that
+// fill the chain's rows of the row -> hit column) and builds the three-point
+// seed.  It leaves the seed in tk_param, the chain's last row in
+// tk_info[2T + i] and 0 (seeded) or -1 (no seed) in tk_info[i].
+// k_up: chain fit and outward extension, one lane per tracklet; it hands the
+// refit its start (below) and counts the tracklet in its (sector, outermost
+// row) bucket.
+// k_sort: bucket offsets (an exclusive scan) and a scatter of the tracklet
+// indices into bucket order (the order inside a bucket does not matter: every
+// tracklet's refit is independent of the others).
+// k_down: the inward refit, one lane per tracklet in bucket order; stores the
+// tracklet.
+// k_guard: the covariance guard over every stored tracklet.
+//
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8),
-// each with its own L2.  Tracklets are ordered by sector, so each XCD is given
-// one contiguous eighth of the tracklets: its lanes then search the row grids
-// of a few sectors only, which stay resident in that XCD's L2.
-__global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
-  __shared__ RowK lrows[kMaxRows];
+// each with its own L2.  Tracklets (and buckets) are ordered by sector, so each
+// XCD is given one contiguous eighth of them: its lanes then search the row
+// grids of a few sectors only, which stay resident in that XCD's L2.
+__global__ void __launch_bounds__(kThreads) k_seed(DevPtrs d, KfConst k) {
+  __shared__ float lx[kMaxRows];
   const uint32_t nt = min(d.hdr->n_starts, d.tcap);
   const uint32_t R = d.R, T = d.tcap;
+  // the bucket counts of k_up start at zero (the C4 row counts are not used after C4)
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < d.SR; q += gridDim.x * blockDim.x) d.row_nstart[q] = 0;
   const XcdSched sch = xcd_sched(nt);
   if (sch.first >= sch.end) return;   // the grid is sized for the tracklet capacity
-  load_rows(d, lrows);
-  unsigned long long my_steps = 0;
+  for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) lx[r] = d.rows[r].x;
+  __syncthreads();
   for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
     const uint32_t i = vb * kThreads + threadIdx.x;
     if (i >= nt) continue;
-    const uint32_t sr0 = d.start_sr[i];
-    const uint32_t sec = sr0 / R, r0 = sr0 % R, srb = sec * R;
-    const SectorConst sc = d.secs[sec];
+    const uint32_t r0 = d.start_sr[i] % R;
     int32_t* H = d.tk_rowhit + i;     // row r at H[r * T]
-    // chain walk
-    int32_t p = (int32_t)d.start_pos[i];
+    const int32_t p0 = (int32_t)d.start_pos[i];
+    int32_t p = p0, plast = p0;
     uint32_t n = 0;
-    int32_t plast = p;
     while (p >= 0 && r0 + n < R) {   // links step one row outward, so a chain ends before row R
       H[(size_t)(r0 + n) * T] = p;
       plast = p;
@@ -478,77 +524,204 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
     const uint32_t m = (n - 1) / 2, rl = r0 + n - 1;
     const int32_t pm = H[(size_t)(r0 + m) * T];
     Trk t;
-    const float2 h0 = d.syz[d.start_pos[i]];
-    const float zref = h0.y;
-    if (!seed3(lrows[r0].x, h0, lrows[r0 + m].x, d.syz[pm], lrows[rl].x, d.syz[plast], k, t)) {
-      d.tk_info[i] = -1;
-      continue;
+    const bool ok = seed3(lx[r0], d.syz[p0], lx[r0 + m], d.syz[pm], lx[rl], d.syz[plast], k, t);
+    if (ok) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) d.tk_param[(size_t)q * T + i] = float(t.p[q]);   // seed3 works in float32
     }
+    d.tk_info[2 * T + i] = (int32_t)rl;
+    d.tk_info[i] = ok ? 0 : -1;
+  }
+}
+
+// atomicAdd(&ctr[key], 1) for every lane with `on`, one atomic per distinct
+// key in the wave (many tracklets share a bucket, and the atomics of one
+// address serialize); returns the lane's slot (the counter before its add).
+// Called by all lanes of the wave.
+__device__ __forceinline__ uint32_t wave_claim(uint32_t* ctr, uint32_t key, bool on) {
+  const uint32_t lane = threadIdx.x % kWave;
+  uint32_t slot = 0;
+  unsigned long long todo = __ballot(on);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const uint32_t lk = (uint32_t)__shfl((int)key, leader, kWave);
+    const unsigned long long grp = __ballot(on && key == lk) & todo;
+    uint32_t base = 0;
+    if ((int)lane == leader) base = atomicAdd(&ctr[lk], (uint32_t)__popcll(grp));
+    base = (uint32_t)__shfl((int)base, leader, kWave);
+    if ((grp >> lane) & 1ull) slot = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+    todo &= ~grp;
+  }
+  return slot;
+}
+
+// Hand-off from k_up to k_down, per tracklet i, in the rows of tk_cov (free
+// until the tracklet is stored, by the lane that has read its hand-off), as
+// 32-bit words at word w * T + i: 0-5 sin phi, tan lambda and q/pT at the
+// outermost hit (double, low word first), 6-7 that hit's (y, z), 8 the
+// outermost row, 9 the start row r0, 10 z_ref, 11 the sector.
+enum : int { kHoPout = 0, kHoHit = 6, kHoRout = 8, kHoR0 = 9, kHoZref = 10, kHoSec = 11 };
+
+__device__ __forceinline__ void put_word(const DevPtrs& d, int w, uint32_t i, uint32_t v) {
+  reinterpret_cast<uint32_t*>(d.tk_cov)[(size_t)w * d.tcap + i] = v;
+}
+__device__ __forceinline__ uint32_t get_word(const DevPtrs& d, int w, uint32_t i) {
+  return reinterpret_cast<const uint32_t*>(d.tk_cov)[(size_t)w * d.tcap + i];
+}
+
+// Chain fit and outward extension of tracklet i (seeded); false if the chain
+// fit fails, else the hand-off is written and key is its refit bucket.
+__device__ __forceinline__ bool up_one(const DevPtrs& d, const KfConst& k, const RowK* lrows, uint32_t i,
+                                       uint32_t& key, uint32_t& steps) {
+  const uint32_t R = d.R, T = d.tcap;
+  const uint32_t sr0 = d.start_sr[i];
+  const uint32_t sec = sr0 / R, srb = sec * R, r0 = sr0 - srb;
+  const SectorConst sc = d.secs[sec];
+  const uint32_t rl = (uint32_t)d.tk_info[2 * T + i];
+  int32_t* H = d.tk_rowhit + i;     // row r at H[r * T]
+  float2 ho = d.syz[d.start_pos[i]];   // the outermost hit so far
+  const float zref = ho.y;
+  Trk t;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) t.p[q] = par_t(d.tk_param[(size_t)q * T + i]);
+  set_c0(t, k);
+  float chi2 = 0.0f, xprev = lrows[r0].x;
+  par_t pout[3] = {t.p[2], t.p[3], t.p[4]};
+  uint32_t rout = rl;
+  int miss = 0;
+  bool failed = false;
+  // chain fit and outward extension, one row per iteration; the chain hit of
+  // the next row (its index one more row ahead) and the next row's grid word
+  // are loaded while this row is stepped
+  const int32_t hk1 = r0 + 1 <= rl ? H[(size_t)(r0 + 1) * T] : -1;
+  float2 hnx = hk1 >= 0 ? d.syz[hk1] : make_float2(0.0f, 0.0f);
+  int32_t hk2 = r0 + 2 <= rl ? H[(size_t)(r0 + 2) * T] : -1;
+  uint2 mnx = r0 + 1 < R && r0 + 1 > rl ? d.row_meta[srb + r0 + 1] : make_uint2(0u, 0u);
+  for (uint32_t r = r0 + 1; r < R; ++r) {
+    const bool chain = r <= rl;
+    const float2 hc = hnx;
+    const uint2 meta = mnx;
+    hnx = hk2 >= 0 ? d.syz[hk2] : make_float2(0.0f, 0.0f);
+    hk2 = r + 2 <= rl ? H[(size_t)(r + 2) * T] : -1;
+    if (r + 1 < R && r + 1 > rl) mnx = d.row_meta[srb + r + 1];
+    ++steps;
+    const RowK rk = lrows[r];
+    const bool pok = propagate<true>(t, rk.x - xprev, k);
+    xprev = rk.x;
+    if (chain && !pok) {
+      failed = true;
+      break;
+    }
+    if (!chain && (!pok || fabs_(t.p[0]) > rk.half_y + k.margin)) break;
+    int32_t h = 0;   // chain rows hold a hit
+    float2 hm = hc;
+    if (!chain) {
+      h = search_m(d, meta, rk, sc, t, k, zref, hm);
+      H[(size_t)r * T] = h;
+    }
+    if (h >= 0) {
+      update(t, hm.x, hm.y - zref, k, chi2);
+      if (r >= rl) {
+        pout[0] = t.p[2];
+        pout[1] = t.p[3];
+        pout[2] = t.p[4];
+        rout = r;
+        ho = hm;
+        miss = 0;
+      }
+    } else if (++miss > k.max_miss) {
+      break;
+    }
+  }
+  if (failed) {
+    d.tk_info[i] = -2;   // the chain fit failed: no tracklet
+    return false;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(pout[q]);
+    put_word(d, kHoPout + 2 * q, i, (uint32_t)b);
+    put_word(d, kHoPout + 2 * q + 1, i, (uint32_t)(b >> 32));
+  }
+  put_word(d, kHoHit, i, (uint32_t)__float_as_int(ho.x));
+  put_word(d, kHoHit + 1, i, (uint32_t)__float_as_int(ho.y));
+  put_word(d, kHoRout, i, rout);
+  put_word(d, kHoR0, i, r0);
+  put_word(d, kHoZref, i, (uint32_t)__float_as_int(zref));
+  put_word(d, kHoSec, i, sec);
+  key = srb + rout;
+  return true;
+}
+
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_up(DevPtrs d, KfConst k) {
+  __shared__ RowK lrows[kMaxRows];
+  const uint32_t nt = min(d.hdr->n_starts, d.tcap);
+  const XcdSched sch = xcd_sched(nt);
+  if (sch.first >= sch.end) return;   // the grid is sized for the tracklet capacity
+  load_rows(d, lrows);
+  uint32_t steps = 0;
+  for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
+    const uint32_t i = vb * kThreads + threadIdx.x;
+    bool on = i < nt && d.tk_info[i] >= 0;
+    uint32_t key = 0;
+    if (on) on = up_one(d, k, lrows, i, key, steps);
+    (void)wave_claim(d.row_nstart, key, on);   // count the tracklet in its refit bucket
+  }
+  uint32_t sum = steps;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) sum += (uint32_t)__shfl_xor((int)sum, off, kWave);
+  if (threadIdx.x == 0 && sum) atomicAdd(&d.hdr->n_steps, (unsigned long long)sum);
+}
+
+// Scatter of the refit tracklets into (sector, outermost row) order; k5_off
+// holds the exclusive scan of the bucket counts (total at [SR]) and serves as
+// the buckets' fill cursors.
+__global__ void __launch_bounds__(256) k_sort(DevPtrs d) {
+  const uint32_t nt = min(d.hdr->n_starts, d.tcap), R = d.R;
+  for (uint32_t b = blockIdx.x * blockDim.x; b < nt; b += gridDim.x * blockDim.x) {   // wave-uniform bounds
+    const uint32_t i = b + threadIdx.x;
+    const bool on = i < nt && d.tk_info[i] >= 0;
+    const uint32_t key = on ? get_word(d, kHoSec, i) * R + get_word(d, kHoRout, i) : 0u;
+    const uint32_t slot = wave_claim(d.k5_off, key, on);
+    if (on) d.k5_perm[slot] = i;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) k_down(DevPtrs d, KfConst k) {
+  __shared__ RowK lrows[kMaxRows];
+  const uint32_t nv = d.k5_off[d.SR];   // refit tracklets (the scan total; the scatter moves only [0, SR))
+  const uint32_t R = d.R, T = d.tcap;
+  const XcdSched sch = xcd_sched(nv);
+  if (sch.first >= sch.end) return;   // the grid is sized for the tracklet capacity
+  load_rows(d, lrows);
+  uint32_t steps = 0;
+  for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
+    const uint32_t j = vb * kThreads + threadIdx.x;
+    if (j >= nv) continue;
+    const uint32_t i = d.k5_perm[j];
+    Trk t;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const unsigned long long b = (unsigned long long)get_word(d, kHoPout + 2 * q, i) |
+                                   ((unsigned long long)get_word(d, kHoPout + 2 * q + 1, i) << 32);
+      t.p[2 + q] = __longlong_as_double((long long)b);
+    }
+    const float hy = __int_as_float((int)get_word(d, kHoHit, i)), hz = __int_as_float((int)get_word(d, kHoHit + 1, i));
+    const uint32_t rout = get_word(d, kHoRout, i), r0 = get_word(d, kHoR0, i);
+    const float zref = __int_as_float((int)get_word(d, kHoZref, i));
+    const uint32_t sec = get_word(d, kHoSec, i), srb = sec * R;
+    const SectorConst sc = d.secs[sec];
+    int32_t* H = d.tk_rowhit + i;     // row r at H[r * T]
+    // inward refit from the outermost hit, fresh covariance
+    t.p[0] = hy;
+    t.p[1] = hz - zref;
     set_c0(t, k);
     float chi2 = 0.0f;
-    bool ok = true;
-    float xprev = lrows[r0].x;
-    // chain fit (no gate); the next chain hit is loaded while this row is fitted
-    float2 hnx = r0 + 1 <= rl ? d.syz[H[(size_t)(r0 + 1) * T]] : make_float2(0.0f, 0.0f);
-    for (uint32_t r = r0 + 1; r <= rl; ++r) {
-      const float2 h = hnx;
-      if (r + 1 <= rl) hnx = d.syz[H[(size_t)(r + 1) * T]];
-      const float x = lrows[r].x;
-      if (!propagate<false>(t, x - xprev, k)) {
-        ok = false;
-        break;
-      }
-      xprev = x;
-      update(t, h.x, h.y - zref, k, chi2);
-    }
-    if (!ok) {
-      d.tk_info[i] = -2;
-      continue;
-    }
-    uint32_t steps = n - 1;
-    // upward extension
-    par_t pout[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
-    uint32_t rout = rl;
-    int miss = 0;
-    uint2 mnx = rl + 1 < R ? d.row_meta[srb + rl + 1] : make_uint2(0u, 0u);   // next row's grid word, one row ahead
-    for (uint32_t r = rl + 1; r < R; ++r) {
-      const uint2 meta = mnx;
-      if (r + 1 < R) mnx = d.row_meta[srb + r + 1];
-      const RowK rk = lrows[r];
-      ++steps;
-      if (!propagate<false>(t, rk.x - xprev, k)) break;
-      xprev = rk.x;
-      if (fabs_(t.p[0]) > rk.half_y + k.margin) break;
-      float2 hm = make_float2(0.0f, 0.0f);
-      const int32_t h = search_m(d, meta, rk, sc, t, k, zref, hm);
-      H[(size_t)r * T] = h;
-      if (h >= 0) {
-        update(t, hm.x, hm.y - zref, k, chi2);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) pout[q] = t.p[q];
-        rout = r;
-        miss = 0;
-      } else if (++miss > k.max_miss) {
-        break;
-      }
-    }
-    // downward refit from the outermost hit, fresh covariance
-    {
-      const float2 ho = d.syz[H[(size_t)rout * T]];
-#pragma unroll
-      for (int q = 2; q < 5; ++q) t.p[q] = pout[q];
-      t.p[0] = ho.x;
-      t.p[1] = ho.y - zref;
-    }
-    set_c0(t, k);
-    chi2 = 0.0f;
     int nh = 1;
     Snap snap = snap_of(t);
     uint32_t rin = rout;
-    xprev = lrows[rout].x;
-    miss = 0;
+    float xprev = lrows[rout].x;
+    int miss = 0;
     // the outward pass's hit of the next row and its coordinates are loaded one
     // and two rows ahead, the next row's grid word one row ahead
     auto known = [&](int r) { return r >= (int)r0 && r >= 0 ? H[(size_t)r * T] : -1; };
@@ -565,15 +738,13 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
       if (r >= 1) mA = d.row_meta[srb + (uint32_t)r - 1];
       const RowK rk = lrows[r];
       ++steps;
-      if (!propagate<false>(t, rk.x - xprev, k)) break;
+      if (!propagate<true>(t, rk.x - xprev, k)) break;
       xprev = rk.x;
       const bool below = (uint32_t)r < r0;
       if (below && fabs_(t.p[0]) > rk.half_y + k.margin) break;
       int32_t h = hk;
       float2 hm = vk;
-      if (h < 0) {
-        h = search_m(d, meta, rk, sc, t, k, zref, hm);
-      }
+      if (h < 0) h = search_m(d, meta, rk, sc, t, k, zref, hm);
       H[(size_t)r * T] = h;
       if (h >= 0) {
         update(t, hm.x, hm.y - zref, k, chi2);
@@ -585,10 +756,12 @@ __global__ void __launch_bounds__(kThreads) k_tracklets(DevPtrs d, KfConst k) {
         break;
       }
     }
-    store_tracklet(d, i, nh, rin, rout, r0, snap, chi2, zref);
-    my_steps += steps;
+    store_tracklet<false>(d, i, nh, rin, rout, r0, snap, chi2, zref);
   }
-  if (my_steps) atomicAdd(&d.hdr->n_steps, my_steps);
+  uint32_t sum = steps;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) sum += (uint32_t)__shfl_xor((int)sum, off, kWave);
+  if (threadIdx.x == 0 && sum) atomicAdd(&d.hdr->n_steps, (unsigned long long)sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -917,7 +1090,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
       --rr;
     }
     if (ok) {
-      store_tracklet(d, i, nh, rin, rout, r0, snap, chi2, zref);
+      store_tracklet<true>(d, i, nh, rin, rout, r0, snap, chi2, zref);
       if (half == 0) my_steps += steps;
     }
   }
@@ -963,7 +1136,13 @@ void launch_tracklets(const DevPtrs& d, const KfConst& k, uint32_t max_row_hits,
   }
   uint32_t blocks = (d.tcap + kThreads - 1) / kThreads;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(k_tracklets, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
+  hipLaunchKernelGGL(k_seed, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
+  hipLaunchKernelGGL(k_up, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
+  launch_scan_u32(d.row_nstart, d.k5_off, d.SR, d.scan_blocks, s);
+  const uint32_t sort_blocks = std::min<uint32_t>((d.tcap + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_sort, dim3(sort_blocks), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_down, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
+  hipLaunchKernelGGL(k_guard, dim3(sort_blocks), dim3(256), 0, s, d);
 }
 
 }  // namespace tpc
