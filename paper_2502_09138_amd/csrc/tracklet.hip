@@ -1,14 +1,16 @@
 // K5: tracklet constructor -- step C5 of the tracker definition.
 //
-// One lane per tracklet (chain start).  The helix state p[5] and packed
-// covariance C[15] are accumulated in double registers (see par_t / cov_t);
-// the per-step increments and the Jacobian are float32.  The transport
-// exploits the sparsity of the Jacobian (6 non-trivial entries) and the update
-// uses the Joseph form, which keeps the covariance positive definite on
-// short, strongly curved fits.  The lane walks
-// its chain (dependent up1 gathers), seeds from three chain hits, fits the
-// chain, extends outward through the row grids and refits inward with a fresh
-// covariance, filling gaps and extending below the chain.
+// Each tracklet (chain start) walks its chain (dependent up1 gathers), seeds
+// from three chain hits, fits the chain, extends outward through the row
+// grids and refits inward with a fresh covariance, filling gaps and extending
+// below the chain.  Two schedules compute it: the row-synchronous kernel
+// (k_tracklets_rs, a wave sweeps the rows of one sector in lockstep with each
+// row staged in LDS; for frames whose rows fit the stage) and the
+// lane-per-tracklet pipeline (k_seed, k_up, k_sort, k_down, k_guard; any row
+// size).  The helix state p[5] and packed covariance C[15] are accumulated in
+// double registers (see par_t / cov_t); the per-step increments and the
+// Jacobian are float32.  The transport exploits the sparsity of the Jacobian
+// (6 non-trivial entries).
 //
 // Latency is the bound (each row step is a dependent chain: propagate ->
 // grid lookup -> candidate loads -> update), so the per-row constants are
@@ -65,6 +67,10 @@ __device__ __forceinline__ double frcp(double x) {
   return r * (2.0 - x * r);
 }
 __device__ __forceinline__ double fabs_(double x) { return fabs(x); }
+
+// native vector types: arrays of them stay in registers
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct Trk {
   par_t p[5];
@@ -176,7 +182,10 @@ __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
   return ok;
 }
 
-// Kalman update with a measurement of (y, z), Joseph form.
+// Kalman update with a measurement of (y, z).  The covariance update is the
+// plain C' = C - K H C: in double it keeps far more precision than the
+// parameters need (the Joseph form, which guards the positive definiteness of
+// a float32 recursion, costs 40 more double operations per step).
 __device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst& k, float& chi2) {
   using P = par_t;
   using V = cov_t;
@@ -199,26 +208,10 @@ __device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst
     K1[i] = c0[i] * I01 + c1[i] * I11;
     t.p[i] += P(K0[i] * r0 + K1[i] * r1);
   }
-  // P = (I - K H) C, then C' = P (I - K H)^T + K V K^T on the lower triangle,
-  // grouped as C' = P + D K^T with D = K V - P H^T (columns 0 and 1 of P)
-  V Pm[5][5];
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      const V cij = i >= j ? c[tri(i, j)] : c[tri(j, i)];
-      Pm[i][j] = cij - K0[i] * c0[j] - K1[i] * c1[j];
-    }
-  V D0[5], D1[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    D0[i] = K0[i] * vy - Pm[i][0];
-    D1[i] = K1[i] * vz - Pm[i][1];
-  }
-#pragma unroll
-  for (int i = 0; i < 5; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) c[tri(i, j)] = Pm[i][j] + D0[i] * K0[j] + D1[i] * K1[j];
+    for (int j = 0; j <= i; ++j) c[tri(i, j)] -= K0[i] * c0[j] + K1[i] * c1[j];
   chi2 += float(r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1));
 }
 
@@ -687,8 +680,18 @@ __global__ void __launch_bounds__(256) k_sort(DevPtrs d) {
   }
 }
 
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) k_down(DevPtrs d, KfConst k) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_down(DevPtrs d, KfConst k) {
   __shared__ RowK lrows[kMaxRows];
+  // the state at each lane's innermost hit so far, in the float32 it is stored
+  // in (in LDS rather than registers: four waves per SIMD instead of three)
+  __shared__ f32x4 snap_s[5][kThreads];
+  const uint32_t lane = threadIdx.x;
+  auto save = [&](const Trk& t) {
+    const Snap v = snap_of(t);
+    snap_s[0][lane] = f32x4{v.p[0], v.p[1], v.p[2], v.p[3]};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) snap_s[1 + q][lane] = f32x4{q == 0 ? v.p[4] : v.c[4 * q - 1], v.c[4 * q], v.c[4 * q + 1], v.c[4 * q + 2]};
+  };
   const uint32_t nv = d.k5_off[d.SR];   // refit tracklets (the scan total; the scatter moves only [0, SR))
   const uint32_t R = d.R, T = d.tcap;
   const XcdSched sch = xcd_sched(nv);
@@ -718,7 +721,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
     set_c0(t, k);
     float chi2 = 0.0f;
     int nh = 1;
-    Snap snap = snap_of(t);
+    save(t);
     uint32_t rin = rout;
     float xprev = lrows[rout].x;
     int miss = 0;
@@ -749,12 +752,27 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
       if (h >= 0) {
         update(t, hm.x, hm.y - zref, k, chi2);
         ++nh;
-        snap = snap_of(t);
+        save(t);
         rin = (uint32_t)r;
         if (below) miss = 0;
       } else if (below && ++miss > k.max_miss) {
         break;
       }
+    }
+    Snap snap;
+    const f32x4 w0 = snap_s[0][lane];
+    snap.p[0] = w0.x;
+    snap.p[1] = w0.y;
+    snap.p[2] = w0.z;
+    snap.p[3] = w0.w;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 w = snap_s[1 + q][lane];
+      if (q == 0) snap.p[4] = w.x;
+      else snap.c[4 * q - 1] = w.x;
+      snap.c[4 * q] = w.y;
+      snap.c[4 * q + 1] = w.z;
+      snap.c[4 * q + 2] = w.w;
     }
     store_tracklet<false>(d, i, nh, rin, rout, r0, snap, chi2, zref);
   }
@@ -802,9 +820,6 @@ struct Stage {
   bool fits;
 };
 
-// native vector types: arrays of them stay in registers
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct Prefetch {
   f32x4 yz[kPreYz];
