@@ -2,7 +2,8 @@
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg
 import this module.  The library it loads (``liboracle.so``) is built from
-``tpc_oracle.cpp`` by :func:`build`; it shares no code with the HIP path.
+``tpc_oracle.cpp`` (steps C1..C9) and ``tpc_codec.cpp`` (C10/C11, track-model
+compression) by :func:`build`; it shares no code with the HIP path.
 """
 from __future__ import annotations
 
@@ -24,10 +25,10 @@ def build(force=True):
     """Compile liboracle.so with g++ (-O2, no FP contraction)."""
     if not force and os.path.exists(LIB_PATH):
         return LIB_PATH
-    src = os.path.join(HERE, "tpc_oracle.cpp")
+    srcs = [os.path.join(HERE, "tpc_oracle.cpp"), os.path.join(HERE, "tpc_codec.cpp")]
     tmp = LIB_PATH + ".tmp"
     subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                           "-shared", "-Wall", "-o", tmp, src])
+                           "-shared", "-Wall", "-o", tmp, *srcs])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -87,6 +88,14 @@ def lib():
         L.orc_bin.argtypes = [C.c_float] * 6 + [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_grid_dims.argtypes = [C.c_uint32, C.c_int, C.c_int64, C.c_int64, C.POINTER(C.c_int),
                                     C.POINTER(C.c_int)]
+        u8p, i16p, u64p = C.POINTER(C.c_uint8), C.POINTER(C.c_int16), C.POINTER(C.c_uint64)
+        L.orc_codec_coef.restype = C.c_int
+        L.orc_codec_coef.argtypes = [fp, C.c_double, fp]
+        L.orc_codec_encode.restype = C.c_uint64
+        L.orc_codec_encode.argtypes = [C.c_int32, dp, C.c_double, C.c_float, C.c_float, C.c_uint32, u32p, u32p, fp, fp,
+                                       C.c_uint64, fp, fp, u32p, C.c_uint32, fp, u8p, i16p, fp, u8p, fp, u64p]
+        L.orc_codec_decode.argtypes = [C.c_int32, dp, C.c_float, C.c_float, C.c_uint32, u32p, fp, fp, u8p, i16p, fp,
+                                       fp, fp]
         _lib = L
     return _lib
 
@@ -298,3 +307,63 @@ def unpack_cov(c15):
             M[i, j] = M[j, i] = c15[k]
             k += 1
     return M
+
+
+# ---- C10/C11: track-model compression (tpc_codec.h) ----
+CODEC_ESCAPE = -32768
+
+
+def codec_coef(param, bz):
+    """Model coefficients (a0, a1, a2, b0, b1, b2) of one track from its float32 parameters; None if no model."""
+    p = np.ascontiguousarray(param, np.float32)
+    out = np.zeros(6, np.float32)
+    rc = lib().orc_codec_coef(_ptr(p, C.c_float), float(bz), _ptr(out, C.c_float))
+    return None if rc else out
+
+
+def codec_encode(row_x, bz, q_y, q_z, first, ids, x_ref, param, y, z, row_offsets):
+    """C10 over a frame's tracks (arrays as tpc_tracks holds them); returns a dict with the stream."""
+    row_x = np.ascontiguousarray(row_x, np.float64)
+    first = np.ascontiguousarray(first, np.uint32)
+    ids = np.ascontiguousarray(ids, np.uint32)
+    x_ref = np.ascontiguousarray(x_ref, np.float32)
+    param = np.ascontiguousarray(param, np.float32).reshape(-1)
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    ro = np.ascontiguousarray(row_offsets, np.uint32)
+    nt, nc, n = len(first) - 1, len(ids), len(y)
+    coef = np.zeros(6 * nt, np.float32)
+    row = np.zeros(nc, np.uint8)
+    code = np.zeros(2 * nc, np.int16)
+    raw = np.zeros(2 * nc, np.float32)
+    un_row = np.zeros(n, np.uint8)
+    un_yz = np.zeros(2 * n, np.float32)
+    nu = C.c_uint64(0)
+    esc = lib().orc_codec_encode(len(row_x), _ptr(row_x, C.c_double), float(bz), float(q_y), float(q_z), nt,
+                                 _ptr(first, C.c_uint32), _ptr(ids, C.c_uint32), _ptr(x_ref, C.c_float),
+                                 _ptr(param, C.c_float), n, _ptr(y, C.c_float), _ptr(z, C.c_float),
+                                 _ptr(ro, C.c_uint32), len(ro) - 1, _ptr(coef, C.c_float), _ptr(row, C.c_uint8),
+                                 _ptr(code, C.c_int16), _ptr(raw, C.c_float), _ptr(un_row, C.c_uint8),
+                                 _ptr(un_yz, C.c_float), C.byref(nu))
+    k = int(nu.value)
+    return dict(coef=coef.reshape(-1, 6), x_ref=x_ref, first=first, row=row, code=code.reshape(-1, 2),
+                raw=raw.reshape(-1, 2), un_row=un_row[:k], un_yz=un_yz[:2 * k].reshape(-1, 2), n_escaped=int(esc))
+
+
+def codec_decode(row_x, q_y, q_z, stream):
+    """C11: (y, z) of the track clusters of a stream, in stream order."""
+    row_x = np.ascontiguousarray(row_x, np.float64)
+    first = np.ascontiguousarray(stream["first"], np.uint32)
+    coef = np.ascontiguousarray(stream["coef"], np.float32).reshape(-1)
+    x_ref = np.ascontiguousarray(stream["x_ref"], np.float32)
+    row = np.ascontiguousarray(stream["row"], np.uint8)
+    code = np.ascontiguousarray(stream["code"], np.int16).reshape(-1)
+    raw = np.ascontiguousarray(stream["raw"], np.float32).reshape(-1)
+    nc = len(row)
+    yo = np.zeros(nc, np.float32)
+    zo = np.zeros(nc, np.float32)
+    lib().orc_codec_decode(len(row_x), _ptr(row_x, C.c_double), float(q_y), float(q_z), len(first) - 1,
+                           _ptr(first, C.c_uint32), _ptr(x_ref, C.c_float), _ptr(coef, C.c_float),
+                           _ptr(row, C.c_uint8), _ptr(code, C.c_int16), _ptr(raw, C.c_float),
+                           _ptr(yo, C.c_float), _ptr(zo, C.c_float))
+    return yo, zo
