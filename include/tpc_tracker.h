@@ -108,6 +108,28 @@
  *     crosses a sector edge; result at the innermost cluster of the first
  *     segment, chi2 of the pass, ndf = 2*nClusters - 5 (-1 if a rotation or
  *     propagation fails; the chain then keeps its first segment's result).
+ * C10 Track-model encoding (the paper names TPC data compression as the
+ *     farm's main task -- abstract; Introduction and its table of processing
+ *     shares -- and the track-model decoding as a step moved to the GPU --
+ *     section on online and offline processing -- without giving a format;
+ *     this is the project's definition).  Per C7 track (parameters p = (y, z,
+ *     s = sin phi, T = tan lambda, q/pT) at x_ref as stored, float32), model
+ *     coefficients computed in double and rounded to float32 once:
+ *       kappa = (-c_B * Bz) * q/pT, c = sqrt(1 - s*s), ic = 1/c, ic3 = ic*ic*ic,
+ *       a = (y, s*ic, 0.5*kappa*ic3), b = (z, T*ic, ((0.5*T)*s)*kappa*ic3)
+ *     (the helix to second order in u = x - x_ref; |s| >= 1: all zero and
+ *     every cluster of the track escaped).  Per track cluster (row r, input
+ *     (y_m, z_m)), float32, each operation rounded, no fused multiply-add:
+ *       u = X_r - x_ref; p_y = a0 + u*(a1 + u*a2), p_z likewise with b;
+ *       v_y = (y_m - p_y) * float32(1/q_y), v_z likewise;
+ *       if |v_y| <= 32767 and |v_z| <= 32767: (k_y, k_z) = (rint(v_y),
+ *       rint(v_z)) (half to even), else k_y = TPC_CODEC_ESCAPE, k_z = 0 and
+ *       (y_m, z_m) stored raw.
+ *     Clusters on no track are stored raw (row, y, z) in input order.
+ * C11 Decoding: y = p_y + k_y*q_y, z = p_z + k_z*q_z (float32, rounded, no
+ *     fused multiply-add); escaped and unassigned clusters are their raw
+ *     values.  A decoded cluster lies within q/2 (plus float32 rounding) of
+ *     the encoded one.
  *
  * Floating point: C1, C2 and the C6 fraction test are exact float32
  * definitions (bit-identical results expected).  C5 runs in float32 on the
@@ -129,7 +151,7 @@
 extern "C" {
 #endif
 
-#define TPC_ABI_VERSION 2u
+#define TPC_ABI_VERSION 3u
 #define TPC_MAX_ROWS 255
 #define TPC_MAX_ROW_HITS 65535u       /* clusters per (sector, row) */
 #define TPC_MAX_COORD 16384.0f        /* |y|, |z| bound (cm) for exact grid searches */
@@ -319,6 +341,53 @@ typedef struct {
   const int32_t* ndf;              /* [n_chains] */
 } tpc_merged;
 tpc_status tpc_merge_sectors(tpc_tracker* t, uint64_t request_id, const int32_t* sector_phys, tpc_merged* out);
+
+/* ---- C10 / C11: track-model compression ---- */
+#define TPC_CODEC_ESCAPE (-32768)
+
+/* A compressed frame.  All arrays are DEVICE memory owned by the caller:
+ * coef [6*n_tracks] (a0, a1, a2, b0, b1, b2 per track), x_ref [n_tracks],
+ * first [n_tracks+1] (offsets of each track's clusters), row [n_track_clusters]
+ * (pad row), code [2*n_track_clusters] (k_y, k_z), raw [2*n_track_clusters]
+ * ((y, z) of escaped clusters, 0 elsewhere), un_row [n_unassigned] and un_yz
+ * [2*n_unassigned] (clusters on no track, input order; the encoder needs room
+ * for n_clusters of the frame). */
+typedef struct {
+  float* coef;
+  float* x_ref;
+  uint32_t* first;
+  uint8_t* row;
+  int16_t* code;
+  float* raw;
+  uint8_t* un_row;
+  float* un_yz;
+} tpc_codec_stream;
+
+typedef struct {
+  uint32_t n_tracks;
+  uint64_t n_track_clusters;
+  uint64_t n_unassigned;
+  uint64_t n_escaped;
+} tpc_codec_counts;
+
+/* C10 on the tracks of a completed request (before its release; the request's
+ * input arrays must still hold the clusters).  q_y, q_z: residual quanta (cm,
+ * finite, > 0).  Runs on the tracker's stream and waits for it; *counts
+ * receives the stream's sizes.  The stream arrays are sized by the caller from
+ * the request's track counts (tpc_get_tracks) and the frame's cluster count.
+ * Uses the request's workspace for flags (its C2 and C6 intermediates are
+ * overwritten).  TPC_E_INVAL for an unknown request, bad quanta or NULL
+ * arrays; TPC_E_INPUT/TPC_E_CAPACITY if the request failed. */
+tpc_status tpc_encode_tracks(tpc_tracker* t, uint64_t request_id, float q_y, float q_z, const tpc_codec_stream* out,
+                             tpc_codec_counts* counts);
+
+/* C11: decodes a stream (device arrays, counts as returned by the encoder,
+ * the same quanta) into DEVICE arrays y_out, z_out, row_out of
+ * n_track_clusters + n_unassigned entries: the track clusters in stream
+ * order, then the unassigned ones.  Needs only the tracker's geometry (no
+ * request); runs on the tracker's stream and waits for it. */
+tpc_status tpc_decode_tracks(tpc_tracker* t, const tpc_codec_stream* in, const tpc_codec_counts* counts, float q_y,
+                             float q_z, float* y_out, float* z_out, uint8_t* row_out);
 
 /* Waits for the request and frees its slot. */
 tpc_status tpc_release(tpc_tracker* t, uint64_t request_id);

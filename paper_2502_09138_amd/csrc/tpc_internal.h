@@ -49,6 +49,8 @@ struct ResultHeader {
   uint32_t pad0;
   uint64_t n_track_clusters;
   uint64_t n_steps;        // row steps taken by all tracklet lanes (C5 work measure)
+  uint32_t codec_escaped;  // clusters the last C10 encoding stored raw
+  uint32_t pad1;
 };
 
 // All device pointers of one request.
@@ -145,6 +147,57 @@ struct MergeArgs {
   double dy, dz, dsinphi, dtanl, dqpt; // C8 windows
 };
 
+// C10 track-model encoding of a completed request's tracks.
+struct CodecArgs {
+  // the request's tracks (C7 outputs in the workspace) and clusters
+  const float* param;          // [5 * n_tracks] track-major
+  const float* xref_in;        // [n_tracks]
+  const uint32_t* first_in;    // [n_tracks + 1]
+  const uint32_t* clusters;    // [n_cl] input cluster ids
+  uint32_t n_tracks;
+  uint64_t n_cl;
+  const uint32_t* row_off;     // [SR + 1] input-order row offsets
+  uint32_t SR, R, N;
+  const RowConst* rows;        // [R] (x)
+  const float* y;              // [N] input coordinates
+  const float* z;
+  double bk;                   // -c_B * Bz
+  float inv_qy, inv_qz;        // float32(1 / q)
+  // stream (caller's device arrays)
+  float* coef;                 // [6 * n_tracks]
+  float* x_ref;                // [n_tracks]
+  uint32_t* first;             // [n_tracks + 1]
+  uint8_t* row;                // [n_cl]
+  int16_t* code;               // [2 * n_cl]
+  float* raw;                  // [2 * n_cl]
+  uint8_t* un_row;             // [N]
+  float* un_yz;                // [2 * N]
+  // workspace scratch
+  uint32_t* unf;               // [N] 1 = on no track
+  uint32_t* row_cnt;           // [SR] clusters on no track per (sector, row)
+  uint32_t* row_pos;           // [SR + 1] exclusive scan of row_cnt
+  uint32_t* n_escaped;
+};
+
+// C11 decoding of a stream into cluster arrays.
+struct DecodeArgs {
+  const float* coef;
+  const float* x_ref;
+  const uint32_t* first;
+  const uint8_t* row;
+  const int16_t* code;
+  const float* raw;
+  const uint8_t* un_row;
+  const float* un_yz;
+  uint32_t n_tracks;
+  uint64_t n_cl, n_un;
+  const RowConst* rows;
+  float q_y, q_z;
+  float* y_out;                // [n_cl + n_un]
+  float* z_out;
+  uint8_t* row_out;
+};
+
 constexpr int kScanBlock = 1024;                   // elements per scan block (256 threads x 4)
 constexpr int kScanMaxBlocks = 8192;               // supports scans of up to 8M elements
 
@@ -155,6 +208,8 @@ void launch_clean_starts(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s)
 void launch_tracklets(const DevPtrs& d, const KfConst& k, uint32_t max_row_hits, hipStream_t s);
 void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipStream_t s);
 void launch_merge(const DevPtrs& d, const MergeArgs& m, const KfConst& k, uint32_t n_tracks, hipStream_t s);
+void launch_codec_encode(const CodecArgs& a, unsigned long long* scan_blocks, hipStream_t s);
+void launch_codec_decode(const DecodeArgs& a, hipStream_t s);
 // exclusive scans; n read from *n_dev when n_dev != nullptr (then n_max bounds the grid)
 void launch_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, unsigned long long* blocks, hipStream_t s);
 void launch_scan_u64(const unsigned long long* in, unsigned long long* out, const uint32_t* n_dev, uint32_t n_max,

@@ -555,6 +555,8 @@ __global__ void k_begin(ResultHeader* h) {
   h->error_flags = 0;
   h->n_tracks = 0;
   h->pad0 = 0;
+  h->codec_escaped = 0;
+  h->pad1 = 0;
   h->n_track_clusters = 0;
   h->n_steps = 0;
 }
@@ -912,6 +914,102 @@ tpc_status tpc_merge_sectors(tpc_tracker* t, uint64_t request_id, const int32_t*
   out->cov = (const float*)host(HL.m_cov);
   out->chi2 = (const float*)host(HL.m_chi2);
   out->ndf = (const int32_t*)host(HL.m_ndf);
+  return TPC_OK;
+}
+
+namespace {
+bool good_quantum(float q) { return std::isfinite(q) && q > 0.0f; }
+}  // namespace
+
+tpc_status tpc_encode_tracks(tpc_tracker* t, uint64_t request_id, float q_y, float q_z, const tpc_codec_stream* out,
+                             tpc_codec_counts* counts) {
+  if (!t || !out || !counts) return fail(TPC_E_INVAL, "NULL argument");
+  if (!t->in_flight || request_id != t->cur_id) return fail(TPC_E_INVAL, "unknown request id");
+  if (!good_quantum(q_y) || !good_quantum(q_z)) return fail(TPC_E_INVAL, "quanta must be finite and > 0");
+  if (!out->coef || !out->x_ref || !out->first || !out->row || !out->code || !out->raw || !out->un_row || !out->un_yz)
+    return fail(TPC_E_INVAL, "NULL stream array");
+  HIP_TRY(hipSetDevice(t->device));
+  HIP_TRY(hipEventSynchronize(t->done));
+  const ResultHeader h = *t->h_hdr;
+  if (h.error_flags) return fail(h.error_flags & TPC_ERR_NONFINITE ? TPC_E_INPUT : TPC_E_CAPACITY, "the request failed");
+  const DevPtrs& d = t->d;
+  CodecArgs a{};
+  a.param = d.out_param;
+  a.xref_in = d.out_xref;
+  a.first_in = d.out_first;
+  a.clusters = d.out_clusters;
+  a.n_tracks = h.n_tracks;
+  a.n_cl = h.n_track_clusters;
+  a.row_off = d.row_off;
+  a.SR = t->cur_S * t->caps.R;
+  a.R = t->caps.R;
+  a.N = t->cur_N;
+  a.rows = d.rows;
+  a.y = d.y;
+  a.z = d.z;
+  a.bk = -kCB * t->cfg.bz_tesla;
+  a.inv_qy = (float)(1.0 / (double)q_y);
+  a.inv_qz = (float)(1.0 / (double)q_z);
+  a.coef = out->coef;
+  a.x_ref = out->x_ref;
+  a.first = out->first;
+  a.row = out->row;
+  a.code = out->code;
+  a.raw = out->raw;
+  a.un_row = out->un_row;
+  a.un_yz = out->un_yz;
+  // scratch of the completed request: the C6 ownership words (one per
+  // cluster) and the C4 / K5 per-row counts
+  a.unf = d.W;
+  a.row_cnt = d.row_nstart;
+  a.row_pos = d.k5_off;
+  a.n_escaped = &d.hdr->codec_escaped;
+  hipStream_t st = t->stream;
+  launch_codec_encode(a, d.scan_blocks, st);
+  HIP_TRY(hipGetLastError());
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(&t->h_hdr->codec_escaped);
+  HIP_TRY(hipMemcpyAsync(cnt, a.n_escaped, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&t->h_hdr->pad1, a.row_pos + a.SR, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  counts->n_tracks = a.n_tracks;
+  counts->n_track_clusters = a.n_cl;
+  counts->n_escaped = t->h_hdr->codec_escaped;
+  counts->n_unassigned = a.SR ? t->h_hdr->pad1 : 0;
+  return TPC_OK;
+}
+
+tpc_status tpc_decode_tracks(tpc_tracker* t, const tpc_codec_stream* in, const tpc_codec_counts* counts, float q_y,
+                             float q_z, float* y_out, float* z_out, uint8_t* row_out) {
+  if (!t || !in || !counts || !y_out || !z_out || !row_out) return fail(TPC_E_INVAL, "NULL argument");
+  if (!good_quantum(q_y) || !good_quantum(q_z)) return fail(TPC_E_INVAL, "quanta must be finite and > 0");
+  if ((counts->n_tracks && (!in->coef || !in->x_ref || !in->first)) ||
+      (counts->n_track_clusters && (!in->row || !in->code || !in->raw)) ||
+      (counts->n_unassigned && (!in->un_row || !in->un_yz)))
+    return fail(TPC_E_INVAL, "NULL stream array");
+  if (counts->n_track_clusters && !counts->n_tracks) return fail(TPC_E_INVAL, "track clusters without tracks");
+  HIP_TRY(hipSetDevice(t->device));
+  DecodeArgs a{};
+  a.coef = in->coef;
+  a.x_ref = in->x_ref;
+  a.first = in->first;
+  a.row = in->row;
+  a.code = in->code;
+  a.raw = in->raw;
+  a.un_row = in->un_row;
+  a.un_yz = in->un_yz;
+  a.n_tracks = counts->n_tracks;
+  a.n_cl = counts->n_track_clusters;
+  a.n_un = counts->n_unassigned;
+  a.rows = t->d.rows;
+  a.q_y = q_y;
+  a.q_z = q_z;
+  a.y_out = y_out;
+  a.z_out = z_out;
+  a.row_out = row_out;
+  hipStream_t st = t->stream;
+  if (a.n_cl + a.n_un) launch_codec_decode(a, st);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
   return TPC_OK;
 }
 

@@ -19,7 +19,7 @@ from .config import TrackerConfig
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtpc_tracker.so")
 
-TPC_ABI_VERSION = 2
+TPC_ABI_VERSION = 3
 TPC_OK, TPC_E_INVAL, TPC_E_NOMEM, TPC_E_DEVICE, TPC_E_CAPACITY, TPC_E_NOTREADY, TPC_E_INPUT, TPC_E_BUSY = \
     0, -1, -2, -3, -4, -5, -6, -7
 TPC_IN_DEVICE, TPC_IN_HOST = 0, 1
@@ -89,10 +89,24 @@ class _Merged(C.Structure):
     ]
 
 
+class _CodecStream(C.Structure):
+    _fields_ = [("coef", C.c_void_p), ("x_ref", C.c_void_p), ("first", C.c_void_p), ("row", C.c_void_p),
+                ("code", C.c_void_p), ("raw", C.c_void_p), ("un_row", C.c_void_p), ("un_yz", C.c_void_p)]
+
+
+class _CodecCounts(C.Structure):
+    _fields_ = [("n_tracks", C.c_uint32), ("n_track_clusters", C.c_uint64), ("n_unassigned", C.c_uint64),
+                ("n_escaped", C.c_uint64)]
+
+
+TPC_CODEC_ESCAPE = -32768
+CODEC_FIELDS = ("coef", "x_ref", "first", "row", "code", "raw", "un_row", "un_yz")
+
 EXPORTED = ("tpc_default_config", "tpc_workspace_bytes", "tpc_tracker_create", "tpc_tracker_destroy",
             "tpc_workspace_bytes_for", "tpc_tracker_bind_workspace", "tpc_track_timeframe_scratch",
             "tpc_track_timeframe", "tpc_get_tracks", "tpc_get_tracks_device", "tpc_release", "tpc_last_error", "tpc_debug_copy",
-            "tpc_set_timing", "tpc_get_pass_times", "tpc_set_tracklet_schedule", "tpc_merge_sectors")
+            "tpc_set_timing", "tpc_get_pass_times", "tpc_set_tracklet_schedule", "tpc_merge_sectors",
+            "tpc_encode_tracks", "tpc_decode_tracks")
 
 _lib = None
 
@@ -127,6 +141,11 @@ def load():
     L.tpc_get_tracks_device.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, P(_Tracks)]
     L.tpc_merge_sectors.restype = C.c_int32
     L.tpc_merge_sectors.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, P(_Merged)]
+    L.tpc_encode_tracks.restype = C.c_int32
+    L.tpc_encode_tracks.argtypes = [C.c_void_p, C.c_uint64, C.c_float, C.c_float, P(_CodecStream), P(_CodecCounts)]
+    L.tpc_decode_tracks.restype = C.c_int32
+    L.tpc_decode_tracks.argtypes = [C.c_void_p, P(_CodecStream), P(_CodecCounts), C.c_float, C.c_float, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]
     L.tpc_release.restype = C.c_int32
     L.tpc_release.argtypes = [C.c_void_p, C.c_uint64]
     L.tpc_last_error.restype = C.c_char_p
@@ -276,6 +295,7 @@ class Tracker:
         # borrowed until the request completes; set only once the request is accepted, so a
         # rejected submit (busy, invalid) leaves the in-flight request's inputs referenced
         self._inputs = (y, z, row_offsets, z_lo, z_hi)
+        self._n_clusters = {rid.value: int(f.n_clusters)}
         return rid.value
 
     def get(self, rid, blocking=True):
@@ -333,6 +353,54 @@ class Tracker:
                     param=arr(m.param, 5 * nc, np.float32).reshape(nc, 5),
                     cov=arr(m.cov, 15 * nc, np.float32).reshape(nc, 15), chi2=arr(m.chi2, nc, np.float32),
                     ndf=arr(m.ndf, nc, np.int32))
+
+    def encode(self, rid, q_y, q_z):
+        """C10 on the tracks of completed request rid (before release): the compressed stream as a dict of
+        device tensors (the arrays of tpc_codec_stream, cut to their counts) plus the counts."""
+        torch = self._torch
+        t = self.get_counts(rid)
+        nt, nc, n = int(t["n_tracks"]), int(t["n_track_clusters"]), self._n_clusters[rid]
+        dev = self.device
+        st = dict(coef=torch.empty(6 * max(nt, 1), dtype=torch.float32, device=dev),
+                  x_ref=torch.empty(max(nt, 1), dtype=torch.float32, device=dev),
+                  first=torch.empty(nt + 1, dtype=torch.int32, device=dev),
+                  row=torch.empty(max(nc, 1), dtype=torch.uint8, device=dev),
+                  code=torch.empty(2 * max(nc, 1), dtype=torch.int16, device=dev),
+                  raw=torch.empty(2 * max(nc, 1), dtype=torch.float32, device=dev),
+                  un_row=torch.empty(max(n, 1), dtype=torch.uint8, device=dev),
+                  un_yz=torch.empty(2 * max(n, 1), dtype=torch.float32, device=dev))
+        s = _CodecStream(*[st[k].data_ptr() for k in CODEC_FIELDS])
+        c = _CodecCounts()
+        # the tensors were allocated on torch's current stream: order the tracker's stream after it
+        self._ready.record(torch.cuda.current_stream(self.device))
+        self.stream.wait_event(self._ready)
+        _check(load().tpc_encode_tracks(self._h, rid, float(q_y), float(q_z), C.byref(s), C.byref(c)))
+        nu = int(c.n_unassigned)
+        out = dict(coef=st["coef"][:6 * nt].view(nt, 6), x_ref=st["x_ref"][:nt], first=st["first"],
+                   row=st["row"][:nc], code=st["code"][:2 * nc].view(nc, 2), raw=st["raw"][:2 * nc].view(nc, 2),
+                   un_row=st["un_row"][:nu], un_yz=st["un_yz"][:2 * nu].view(nu, 2))
+        counts = dict(n_tracks=int(c.n_tracks), n_track_clusters=int(c.n_track_clusters), n_unassigned=nu,
+                      n_escaped=int(c.n_escaped))
+        return out, counts
+
+    def decode(self, stream, counts, q_y, q_z):
+        """C11: (y, z, row) device tensors of a stream's clusters (track clusters in stream order, then the
+        unassigned ones)."""
+        torch = self._torch
+        n = counts["n_track_clusters"] + counts["n_unassigned"]
+        y = torch.empty(max(n, 1), dtype=torch.float32, device=self.device)
+        z = torch.empty_like(y)
+        row = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        for k in CODEC_FIELDS:
+            t = stream[k]
+            assert t.is_cuda and t.is_contiguous(), k
+        s = _CodecStream(*[stream[k].data_ptr() if stream[k].numel() else 0 for k in CODEC_FIELDS])
+        c = _CodecCounts(counts["n_tracks"], counts["n_track_clusters"], counts["n_unassigned"], counts["n_escaped"])
+        self._ready.record(torch.cuda.current_stream(self.device))
+        self.stream.wait_event(self._ready)
+        _check(load().tpc_decode_tracks(self._h, C.byref(s), C.byref(c), float(q_y), float(q_z), y.data_ptr(),
+                                        z.data_ptr(), row.data_ptr()))
+        return y[:n], z[:n], row[:n]
 
     def track_and_merge(self, y, z, row_offsets, z_lo, z_hi, sector_phys, *, host=False):
         """One frame through C1..C9: (tracks, merged chains)."""
