@@ -49,11 +49,12 @@ PROFILE_SOURCES = (
 )
 PROFILES = {
     "time_frame": {
-        "digests": ("50dafa9f555f13db346fcd08ad6666c75f4724bb", "ad6bcd87cc9f7c3f0839ae36deca241dbd83786b",
+        "digests": ("cde902349f5835a0e2fe6c7547872a39958995e6", "ad6bcd87cc9f7c3f0839ae36deca241dbd83786b",
                     "8d4ffb5e64cc1810222dbe0c811aa511ffde5df6", "b4b103e57db5db269528a9bdae40217f2bb52ff1",
-                    "870a84e59816aedf636e9f025635fcac579f612b"),
-        "traffic_bytes": {"tracklets": 7_540_940_000, "grid": 294_780_000, "neighbours": 473_960_000},
-        "valu_insts": {"tracklets": 1_239_969_573, "grid": 19_770_947, "neighbours": 310_520_732},
+                    "bf309c15529ec6d7132f1661f16c555d731ea38f"),
+        # tracklets: k_seed + k_up + k_sort + k_down + k_guard; VALU of k_up and k_down (the rest is < 5%)
+        "traffic_bytes": {"tracklets": 7_220_910_000, "grid": 294_330_000, "neighbours": 473_960_000},
+        "valu_insts": {"tracklets": 948_118_308, "grid": 19_770_947, "neighbours": 310_520_732},
         "files": "profiles/time_frame_hbm_traffic.md, profiles/time_frame_sq_counters.md",
     },
 }
@@ -247,6 +248,69 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+def _entropy_bits(v):
+    """Empirical Shannon entropy (bits per symbol) of an integer array."""
+    if len(v) == 0:
+        return 0.0
+    _, c = np.unique(v, return_counts=True)
+    p = c / c.sum()
+    return float(-(p * np.log2(p)).sum())
+
+
+def codec_extra(torch, tr, y, z, ev, q, reps=5):
+    """C10/C11 on the frame's tracks: encode and decode times (HIP events on the tracker stream around each
+    call, which waits for its kernels) and the stream's size against raw float32 (y, z)."""
+    qy, qz = q
+    rid = tr.submit(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+    try:
+        tr.get_counts(rid)
+        enc, dec = [], []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(tr.stream)
+            stream, counts = tr.encode(rid, qy, qz)
+            e1.record(tr.stream)
+            e1.synchronize()
+            enc.append(e0.elapsed_time(e1))
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(tr.stream)
+            out = tr.decode(stream, counts, qy, qz)
+            e1.record(tr.stream)
+            e1.synchronize()
+            dec.append(e0.elapsed_time(e1))
+        code = stream["code"].cpu().numpy()
+        row = stream["row"].cpu().numpy().astype(np.int32)
+        first = stream["first"].cpu().numpy().astype(np.int64)
+        del out
+    finally:
+        tr.release(rid)
+    N = ev.n_clusters
+    nt, nc, nu, ne = counts["n_tracks"], counts["n_track_clusters"], counts["n_unassigned"], counts["n_escaped"]
+    ok = code[:, 0] != -32768
+    # row steps inside a track (the first cluster of each track keeps its row)
+    drow = row.copy()
+    if nc:
+        drow[1:] -= row[:-1]
+        drow[first[:-1][first[:-1] < nc]] = row[first[:-1][first[:-1] < nc]]
+    bits = _entropy_bits(code[ok, 0]) + _entropy_bits(code[ok, 1]) + _entropy_bits(drow)
+    header = nt * (6 * 4 + 4 + 4)
+    raw_part = ne * 8 + nu * 9
+    stream_bytes = header + nc * 5 + raw_part
+    entropy_bytes = header + nc * bits / 8.0 + raw_part
+    raw_bytes = N * 8
+    em, dm = float(np.median(enc)), float(np.median(dec))
+    return {"encode_ms": round(em, 4), "decode_ms": round(dm, 4),
+            "encode_clusters_per_s": round(N / (em * 1e-3), 1), "decode_clusters_per_s": round(N / (dm * 1e-3), 1),
+            "q_cm": [qy, qz], "tracks": nt, "track_clusters": nc, "unassigned": nu, "escaped": ne,
+            "bytes_raw_yz": raw_bytes, "bytes_stream": stream_bytes, "ratio_stream": round(raw_bytes / stream_bytes, 3),
+            "entropy_bits_per_track_cluster": round(bits, 3),
+            "ratio_entropy_coded_estimate": round(raw_bytes / entropy_bytes, 3),
+            "note": "raw = float32 (y, z) per cluster; stream = 32 B per track + row and (k_y, k_z) per track "
+                    "cluster (5 B) + 8 B per escaped + 9 B per unassigned cluster; the entropy estimate replaces "
+                    "the 5 B by the empirical entropy of k_y, k_z and the row step"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +337,8 @@ def main():
     ap.add_argument("--serve-extra", type=float, default=1.0,
                     help="seconds of serving trace in the default run's extras (0 = none)")
     ap.add_argument("--quick", action="store_true", help="headline only: no per-sector, chunk or serving extras")
+    ap.add_argument("--codec", action="store_true", help="with --quick: still measure the track-model codec")
+    ap.add_argument("--codec-q", default="0.01,0.015", help="residual quanta q_y,q_z (cm) of the codec")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sectors and time frames "
@@ -376,7 +442,7 @@ def main():
     value = N * args.steps / elapsed
     pass_ms = {k: float(np.mean(v)) for k, v in bd_acc.items()}
     pass_ms[dominant] = dom_ms   # the dominant pass as timed inside the timed loop
-    k5_name = "k_tracklets_rs (K5, C5)" if tr_schedule_rowsync(args.schedule, ev) else "k_seed + k_fit (K5, C5)"
+    k5_name = "k_tracklets_rs (K5, C5)" if tr_schedule_rowsync(args.schedule, ev) else "k_seed, k_up, k_sort, k_down, k_guard (K5, C5)"
     prof = stored_profile(wl["workload"])
 
     def roof_entry(kernel, pass_name, alg_bytes, issue_bound):
@@ -457,6 +523,9 @@ def main():
             "frames": len(ps), "speedup_of_batched": round(float(np.median(ps)) / (elapsed / args.steps), 2),
             "note": f"the same frame as {ev.n_sectors} requests of one sector each, issued back to back"}
         log(f"bench: per-sector launches: {rec['per_sector_launches']}")
+    if (not args.quick or args.codec) and args.mode == "batched":
+        rec["codec"] = codec_extra(torch, tr, y, z, ev, [float(v) for v in args.codec_q.split(",")])
+        log(f"bench: codec: {rec['codec']}")
     tr.close()
     del tr, y, z
     torch.cuda.empty_cache()
