@@ -223,7 +223,8 @@ void tpc_default_config(tpc_tracker_config* cfg);
 uint64_t tpc_workspace_bytes(const tpc_tracker_config* cfg);
 
 /* Validates cfg (TPC_E_INVAL before any device call), then selects the
- * device, uploads the constant tables and carves the workspace. */
+ * device, uploads the constant tables (the float32 constants of C1, C2 and
+ * C5 derived in double from the geometry and cuts) and carves the workspace. */
 tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out);
 void tpc_tracker_destroy(tpc_tracker* t);
 
@@ -261,9 +262,11 @@ typedef struct {
                                       completes; TPC_IN_HOST: host arrays, copied before return */
 } tpc_timeframe;
 
-/* Enqueues C1..C7 for one time frame on the tracker's stream and returns at
- * once.  Errors in the host-side validation return TPC_E_INVAL and enqueue
- * nothing. */
+/* Enqueues C1..C7 (defined above: the TPC track finding that the paper's
+ * Introduction and Tables 1-3 place at the core of the GPU workload) for one
+ * time frame on the tracker's stream and returns at once.  Errors in the
+ * host-side validation return TPC_E_INVAL and enqueue nothing; device-side
+ * errors are reported by tpc_get_tracks. */
 tpc_status tpc_track_timeframe(tpc_tracker* t, const tpc_timeframe* tf, uint64_t* request_id);
 
 /* For callers that cannot allocate device memory (code under stream capture,
