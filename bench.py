@@ -552,6 +552,35 @@ def main():
                                 "ms_per_step": round(1e3 * float(np.mean(tc)), 4), "n_clusters": evc.n_clusters,
                                 "n_chunks": evc.n_sectors, "tracks": cc["n_tracks"],
                                 "note": "512 sector-sized chunks of log-uniform occupancy (1k-200k), one batched request"}
+        # the knob tuner on this shape class, then the tuned setting timed like the default one
+        tuner = batching.ScheduleTuner(trc, candidates=batching.knob_grid(), repeats=1)
+        choice = tuner.choose(yc, zc, evc.row_offsets, evc.sector_z_lo, evc.sector_z_hi)
+        tt = []
+        for _ in range(5):
+            s0 = time.perf_counter()
+            rid = trc.submit(yc, zc, evc.row_offsets, evc.sector_z_lo, evc.sector_z_hi)
+            trc.get_device(rid)
+            trc.release(rid)
+            tt.append(time.perf_counter() - s0)
+        rec["uneven_chunks"]["tuned"] = {"knobs": choice, "ms_per_step": round(1e3 * float(np.mean(tt)), 4),
+                                         "tuning_runs": tuner.tuned_runs}
+        # the plain path: one request per chunk, back to back
+        trc.set_knobs(schedule=0, select_tile_rows=0, refit_order=0)
+        pc = []
+        czlo = np.asarray(evc.sector_z_lo, np.float32)
+        czhi = np.asarray(evc.sector_z_hi, np.float32)
+        for k in range(3):
+            s0 = time.perf_counter()
+            for sec, a, b, ro in batching.sector_spans(evc.row_offsets):
+                rid = trc.submit(yc[a:b], zc[a:b], ro, czlo[sec:sec + 1], czhi[sec:sec + 1])
+                trc.get_device(rid)
+                trc.release(rid)
+            if k:                       # the first pass warms up the per-chunk shapes
+                pc.append(time.perf_counter() - s0)
+        rec["uneven_chunks"]["per_chunk_launches"] = {
+            "ms_per_step": round(1e3 * float(np.mean(pc)), 4),
+            "value": round(evc.n_clusters * len(pc) / sum(pc), 1), "unit": "clusters/s",
+            "note": "one request per chunk (512), issued back to back (device views, as the batched step)"}
         log(f"bench: uneven_chunks: {rec['uneven_chunks']}")
         trc.close()
         del trc, yc, zc, evc

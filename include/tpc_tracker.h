@@ -424,6 +424,24 @@ tpc_status tpc_debug_copy(tpc_tracker* t, int32_t what, void* host_dst, uint64_t
  * TPC_E_INVAL for other values or while a request is in flight. */
 tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule);
 
+/* Tuning knobs for later requests (results are identical under every
+ * setting; they change speed only, which is what a shape-class autotuner
+ * chooses between):
+ *   TPC_KNOB_TRACKLET_SCHEDULE  0 auto, 1 lane-per-tracklet pipeline, 2
+ *                               row-synchronous (as tpc_set_tracklet_schedule)
+ *   TPC_KNOB_SELECT_TILE_ROWS   0 auto (4 rows, fewer where a block would need
+ *                               more than 16 KB of LDS); 1, 2, 4: rows per C6
+ *                               selector tile, reduced to the largest power of
+ *                               two whose blocks fit 48 KB of LDS (none: the
+ *                               global-memory selector); -1: the global-memory
+ *                               selector
+ *   TPC_KNOB_REFIT_ORDER        0 the lane-per-tracklet pipeline refits in
+ *                               (sector, outermost row) order, 1 in tracklet
+ *                               order
+ * TPC_E_INVAL for an unknown knob or value, or while a request is in flight. */
+enum { TPC_KNOB_TRACKLET_SCHEDULE = 1, TPC_KNOB_SELECT_TILE_ROWS = 2, TPC_KNOB_REFIT_ORDER = 3 };
+tpc_status tpc_set_knob(tpc_tracker* t, int32_t knob, int32_t value);
+
 /* Per-pass timing with HIP events on the tracker's stream, for later requests.
  * pass_mask: bit p times pass p (TPC_N_PASSES passes, in the order below);
  * 0 turns timing off, TPC_TIME_ALL_PASSES times every pass; TPC_E_INVAL for

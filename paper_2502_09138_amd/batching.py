@@ -86,12 +86,25 @@ def shape_class(row_offsets, n_rows=N_ROWS):
     return (b(S), b(mx), b(mean))
 
 
+def knob_grid(schedules=(1, 2), tile_rows=(0, 2, 4, -1), refit_orders=(0, 1)):
+    """Every knob setting to sweep: the refit order matters only for the lane-per-tracklet schedule."""
+    out = []
+    for s in schedules:
+        for r in tile_rows:
+            for o in (refit_orders if s == 1 else (0,)):
+                out.append({"schedule": s, "select_tile_rows": r, "refit_order": o})
+    return out
+
+
 class ScheduleTuner:
-    """Chooses the tracklet schedule per (architecture, shape class); the choice is cached."""
+    """Chooses the tracker's knobs per (architecture, shape class) by timing every candidate setting on
+    the first frame of the class (all passes, HIP events, best of ``repeats``); the choice is cached,
+    optionally in a JSON file.  Candidates are knob dicts (see ``Tracker.set_knobs``) or plain schedule
+    numbers."""
 
     def __init__(self, tracker, candidates=(1, 2), repeats=2, cache_path=None, arch=None):
         self.tracker = tracker
-        self.candidates = tuple(candidates)
+        self.candidates = tuple(c if isinstance(c, dict) else {"schedule": int(c)} for c in candidates)
         self.repeats = repeats
         self.cache_path = cache_path
         self.arch = arch or "gfx950"
@@ -106,26 +119,30 @@ class ScheduleTuner:
         return (self.arch,) + shape_class(row_offsets)
 
     def choose(self, y, z, row_offsets, z_lo, z_hi):
+        """The best knob setting for this frame's shape class (applied to the tracker); with plain
+        schedule candidates, the schedule number."""
         key = self.key(row_offsets)
         if key not in self.cache:
             tr = self.tracker
             best, best_ms = None, float("inf")
-            tr.set_timing(True, passes=("tracklets",))
+            tr.set_timing(True)
             for cand in self.candidates:
-                tr.set_tracklet_schedule(cand)
+                tr.set_knobs(**cand)
                 ms = float("inf")
                 for _ in range(self.repeats):
                     rid = tr.submit(y, z, row_offsets, z_lo, z_hi)
                     tr.get_device(rid)
-                    ms = min(ms, tr.pass_times()["tracklets"])
+                    ms = min(ms, sum(tr.pass_times().values()))
                     tr.release(rid)
                     self.tuned_runs += 1
-                self.timings[(key, cand)] = ms
+                self.timings[(key, json.dumps(cand, sort_keys=True))] = ms
                 if ms < best_ms:
                     best, best_ms = cand, ms
+            tr.set_timing(False)
             self.cache[key] = best
             if self.cache_path:
                 with open(self.cache_path, "w") as f:
                     json.dump({json.dumps(list(k)): v for k, v in self.cache.items()}, f)
-        self.tracker.set_tracklet_schedule(self.cache[key])
-        return self.cache[key]
+        choice = self.cache[key]
+        self.tracker.set_knobs(**choice)
+        return choice["schedule"] if set(choice) == {"schedule"} else choice

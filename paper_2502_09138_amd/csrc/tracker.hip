@@ -49,6 +49,7 @@ constexpr int kMaxDevices = 64;
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kSelectTileWords = 12288;     // 48 KB of LDS per selector tile at most
 constexpr uint32_t kSelectTilePreferred = 4096;  // 16 KB: multi-row tiles above this keep too few tiles resident
+constexpr uint32_t kSelectGlobal = 0xFFFFFFFFu;  // TPC_KNOB_SELECT_TILE_ROWS = -1: the global-memory selector
 
 struct Layout {   // byte offsets of every workspace buffer
   uint64_t row_off, rows, secs, row_dims, row_meta, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
@@ -244,6 +245,7 @@ struct tpc_tracker {
   bool fetched = false;
   uint32_t cur_S = 0, cur_N = 0;
   tpc_tracks out{};
+  uint32_t select_tile_rows = 0;   // TPC_KNOB_SELECT_TILE_ROWS (0 = auto, kSelectGlobal = global selector)
 };
 
 namespace {
@@ -636,15 +638,19 @@ tpc_status enqueue(tpc_tracker* t, const tpc_timeframe* f, uint32_t max_row, uin
   // central event 4 rows 0.126 ms vs 8 rows 0.163 ms; 32-orbit frame 2 rows
   // 1.02 ms vs 4 rows 1.25 ms.)  Per-tile owned counts are bytes, so tiles
   // need at most 255 rows per sector.
+  // A forced tile size (TPC_KNOB_SELECT_TILE_ROWS) starts from the requested
+  // rows and allows the whole kSelectTileWords to every size.
   uint32_t tile_rows = 0, tile_cap = 0;
-  for (uint32_t tr = 4; tr >= 1 && tile_rows == 0 && R <= 255; tr /= 2) {
+  const uint32_t forced = t->select_tile_rows == kSelectGlobal ? 0u : t->select_tile_rows;
+  for (uint32_t tr = forced ? forced : 4; tr >= 1 && tile_rows == 0 && R <= 255 && t->select_tile_rows != kSelectGlobal;
+       tr /= 2) {
     uint32_t mx = 0;
     for (uint32_t s = 0; s < S; ++s)
       for (uint32_t ra = 0; ra < R; ra += tr) {
         const uint32_t rb = std::min(R, ra + tr);
         mx = std::max(mx, f->row_offsets[s * R + rb] - f->row_offsets[s * R + ra]);
       }
-    if (mx <= (tr == 1 ? kSelectTileWords : kSelectTilePreferred)) {
+    if (mx <= (tr == 1 || forced ? kSelectTileWords : kSelectTilePreferred)) {
       tile_rows = tr;
       tile_cap = std::max(mx, 1u);
     }
@@ -1060,6 +1066,26 @@ tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule) {
   t->cfg.tracklet_schedule = schedule;
   t->d.k5_mode = schedule;
   return TPC_OK;
+}
+
+tpc_status tpc_set_knob(tpc_tracker* t, int32_t knob, int32_t value) {
+  if (!t) return fail(TPC_E_INVAL, "tracker is NULL");
+  if (t->in_flight) return fail(TPC_E_INVAL, "a request is in flight");
+  switch (knob) {
+    case TPC_KNOB_TRACKLET_SCHEDULE:
+      return tpc_set_tracklet_schedule(t, value);
+    case TPC_KNOB_SELECT_TILE_ROWS:
+      if (value != 0 && value != 1 && value != 2 && value != 4 && value != -1)
+        return fail(TPC_E_INVAL, "select tile rows must be 0, 1, 2, 4 or -1");
+      t->select_tile_rows = value < 0 ? kSelectGlobal : (uint32_t)value;
+      return TPC_OK;
+    case TPC_KNOB_REFIT_ORDER:
+      if (value != 0 && value != 1) return fail(TPC_E_INVAL, "refit order must be 0 or 1");
+      t->d.k5_refit_order = value;
+      return TPC_OK;
+    default:
+      return fail(TPC_E_INVAL, "unknown knob");
+  }
 }
 
 tpc_status tpc_set_timing(tpc_tracker* t, int32_t pass_mask) {

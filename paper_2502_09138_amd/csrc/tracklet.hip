@@ -692,7 +692,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
     for (int q = 0; q < 4; ++q) snap_s[1 + q][lane] = f32x4{q == 0 ? v.p[4] : v.c[4 * q - 1], v.c[4 * q], v.c[4 * q + 1], v.c[4 * q + 2]};
   };
-  const uint32_t nv = d.k5_off[d.SR];   // refit tracklets (the scan total; the scatter moves only [0, SR))
+  // bucket order: the refit tracklets (the scan total; the scatter moves only
+  // [0, SR)); tracklet order: every tracklet, those without a hand-off skipped
+  const bool sorted = d.k5_refit_order == 0;
+  const uint32_t nv = sorted ? d.k5_off[d.SR] : min(d.hdr->n_starts, d.tcap);
   const uint32_t R = d.R, T = d.tcap;
   const XcdSched sch = xcd_sched(nv);
   if (sch.first >= sch.end) return;   // the grid is sized for the tracklet capacity
@@ -700,8 +703,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
   uint32_t steps = 0;
   for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
     const uint32_t j = vb * kThreads + threadIdx.x;
-    if (j >= nv) continue;
-    const uint32_t i = d.k5_perm[j];
+    if (j >= nv || (!sorted && d.tk_info[j] < 0)) continue;
+    const uint32_t i = sorted ? d.k5_perm[j] : j;
     Trk t;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -1153,9 +1156,11 @@ void launch_tracklets(const DevPtrs& d, const KfConst& k, uint32_t max_row_hits,
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_seed, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
   hipLaunchKernelGGL(k_up, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
-  launch_scan_u32(d.row_nstart, d.k5_off, d.SR, d.scan_blocks, s);
   const uint32_t sort_blocks = std::min<uint32_t>((d.tcap + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_sort, dim3(sort_blocks), dim3(256), 0, s, d);
+  if (d.k5_refit_order == 0) {
+    launch_scan_u32(d.row_nstart, d.k5_off, d.SR, d.scan_blocks, s);
+    hipLaunchKernelGGL(k_sort, dim3(sort_blocks), dim3(256), 0, s, d);
+  }
   hipLaunchKernelGGL(k_down, dim3(xcd_grid(blocks)), dim3(kThreads), 0, s, d, k);
   hipLaunchKernelGGL(k_guard, dim3(sort_blocks), dim3(256), 0, s, d);
 }

@@ -100,13 +100,15 @@ class _CodecCounts(C.Structure):
 
 
 TPC_CODEC_ESCAPE = -32768
+# tuning knobs (tpc_set_knob)
+KNOBS = {"schedule": 1, "select_tile_rows": 2, "refit_order": 3}
 CODEC_FIELDS = ("coef", "x_ref", "first", "row", "code", "raw", "un_row", "un_yz")
 
 EXPORTED = ("tpc_default_config", "tpc_workspace_bytes", "tpc_tracker_create", "tpc_tracker_destroy",
             "tpc_workspace_bytes_for", "tpc_tracker_bind_workspace", "tpc_track_timeframe_scratch",
             "tpc_track_timeframe", "tpc_get_tracks", "tpc_get_tracks_device", "tpc_release", "tpc_last_error", "tpc_debug_copy",
             "tpc_set_timing", "tpc_get_pass_times", "tpc_set_tracklet_schedule", "tpc_merge_sectors",
-            "tpc_encode_tracks", "tpc_decode_tracks")
+            "tpc_encode_tracks", "tpc_decode_tracks", "tpc_set_knob")
 
 _lib = None
 
@@ -153,6 +155,8 @@ def load():
     L.tpc_debug_copy.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint64, P(C.c_uint64)]
     L.tpc_set_tracklet_schedule.restype = C.c_int32
     L.tpc_set_tracklet_schedule.argtypes = [C.c_void_p, C.c_int32]
+    L.tpc_set_knob.restype = C.c_int32
+    L.tpc_set_knob.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     L.tpc_set_timing.restype = C.c_int32
     L.tpc_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.tpc_get_pass_times.restype = C.c_int32
@@ -450,6 +454,15 @@ class Tracker:
         if n.value:
             _check(L.tpc_debug_copy(self._h, what, out.ctypes.data, n.value, C.byref(n)))
         return out
+
+    def set_knobs(self, **knobs):
+        """Tuning knobs for later requests (results identical under every setting): schedule (0 auto,
+        1 lane-per-tracklet pipeline, 2 row-synchronous), select_tile_rows (0 auto, 1, 2, 4, -1 global),
+        refit_order (0 bucket order, 1 tracklet order)."""
+        for name, value in knobs.items():
+            if name not in KNOBS:
+                raise ValueError(f"unknown knob {name}")
+            _check(load().tpc_set_knob(self._h, KNOBS[name], int(value)))
 
     def set_tracklet_schedule(self, schedule):
         """0 auto, 1 one lane per tracklet, 2 row-synchronous (applies to later requests)."""

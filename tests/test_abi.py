@@ -79,6 +79,7 @@ def test_null_arguments_rejected(lib):
     assert lib.tpc_set_tracklet_schedule(None, 1) == trk.TPC_E_INVAL
     assert lib.tpc_encode_tracks(None, 1, 0.01, 0.01, None, None) == trk.TPC_E_INVAL
     assert lib.tpc_decode_tracks(None, None, None, 0.01, 0.01, None, None, None) == trk.TPC_E_INVAL
+    assert lib.tpc_set_knob(None, 1, 0) == trk.TPC_E_INVAL
 
 
 def test_rejected_submit_keeps_the_inflight_inputs(monkeypatch):

@@ -99,3 +99,60 @@ def test_schedule_tuner_caches_per_shape_class(tmp_path):
         assert out.n_tracks > 100 and out.error_flags == 0
     finally:
         tr.close()
+
+
+@pytest.mark.gpu
+def test_every_knob_setting_gives_identical_results():
+    """The tuner's knobs change speed only: every setting of schedule x selector tile rows x refit
+    order gives bit-identical outputs (six sectors of the 32-orbit frame: rows beyond the
+    row-synchronous stage; the central event's first four sectors: rows within it)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_09138_amd.tracker import Tracker
+    dev = torch.device("cuda", 0)
+    for name, ev in (("time_frame sectors 0-5", synth.time_frame(seed=3).sector_slice(range(6))),
+                     ("central_event sectors 0-3", synth.central_event(seed=2).sector_slice(range(4)))):
+        print("case:", name, "N=", ev.n_clusters, flush=True)
+        y = torch.from_numpy(ev.y).to(dev)
+        z = torch.from_numpy(ev.z).to(dev)
+        tr = Tracker(default_config(), max_clusters=ev.n_clusters, max_sectors=ev.n_sectors)
+        try:
+            ref = None
+            for knobs in batching.knob_grid():
+                tr.set_knobs(**knobs)
+                out = tr.track(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+                assert out.error_flags == 0 and out.n_tracks > 100
+                if ref is None:
+                    ref = out
+                    continue
+                for k in ("sector", "start", "first", "cluster_ids", "x_ref", "param", "cov", "chi2", "ndf"):
+                    a, b = getattr(out, k), getattr(ref, k)
+                    if k in ("param", "cov", "chi2", "x_ref"):
+                        a, b = a.view(np.int32), b.view(np.int32)
+                    assert np.array_equal(a, b), (name, knobs, k)
+        finally:
+            tr.close()
+
+
+@pytest.mark.gpu
+def test_knob_tuner_sweeps_the_grid_once_per_shape_class(tmp_path):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_09138_amd.tracker import Tracker
+    ev = synth.uneven_chunks(chunks=[0, 3, 7, 11, 40, 41, 90, 200])
+    dev = torch.device("cuda", 0)
+    y = torch.from_numpy(ev.y).to(dev)
+    z = torch.from_numpy(ev.z).to(dev)
+    tr = Tracker(default_config(), max_clusters=ev.n_clusters, max_sectors=ev.n_sectors)
+    try:
+        grid = batching.knob_grid()
+        tuner = batching.ScheduleTuner(tr, candidates=grid, repeats=1, cache_path=str(tmp_path / "knobs.json"))
+        choice = tuner.choose(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+        print("knob choice", choice, flush=True)
+        assert choice in grid and tuner.tuned_runs == len(grid)
+        assert tuner.choose(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi) == choice
+        assert tuner.tuned_runs == len(grid)
+    finally:
+        tr.close()
