@@ -230,7 +230,7 @@ __device__ __forceinline__ void set_c0(Trk& t, const KfConst& k) {
 // flat sequence of candidate groups per lane (see search_lds); the kGroup loads
 // of a group are issued together.
 constexpr int kGroup = 6;   // measured on the 32-orbit frame: 4 -> 6 is -3.7% in K5, 8 and above slower
-constexpr int kGroupLds = 4;   // the same for the LDS search
+constexpr int kGroupLds = 4;   // candidates per group of the LDS search
 
 __device__ __forceinline__ int32_t search_m(const DevPtrs& d, uint2 meta, const RowK& rk, const SectorConst& sc,
                                             const Trk& t, const KfConst& k, float zref, float2& hv) {
