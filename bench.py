@@ -39,7 +39,8 @@ K2_BYTES_PER_CLUSTER = 18.0     # read own (y, z) + each adjacent row once + bin
 # Stored rocprofv3 figures per workload (commands and tables in profiles/): HBM bytes per launch
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, scaled on a 1 GiB device copy) and VALU wave
 # instructions per launch (SQ_INSTS_VALU).  They hold for the kernel sources with the listed SHA-1
-# digests and are reported as null once a source differs; they are not measured in this run.
+# digests and are reported as null once a source differs, or when the run's knob setting differs from the
+# profiled one; they are not measured in this run.
 PROFILE_SOURCES = (
     "paper_2502_09138_amd/csrc/tracklet.hip",
     "paper_2502_09138_amd/csrc/links.hip",
@@ -63,11 +64,13 @@ PROFILES = {
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def stored_profile(workload):
+def stored_profile(workload, knobs=None):
     import hashlib
     prof = PROFILES.get(workload)
     if prof is None:
         return None
+    if prof.get("knobs") is not None and knobs != prof["knobs"]:
+        return None   # profiled with another knob setting
     for rel, digest in zip(PROFILE_SOURCES, prof["digests"]):
         with open(os.path.join(ROOT, rel), "rb") as f:
             if hashlib.sha1(f.read()).hexdigest() != digest:
@@ -338,6 +341,11 @@ def main():
                     help="seconds of serving trace in the default run's extras (0 = none)")
     ap.add_argument("--quick", action="store_true", help="headline only: no per-sector, chunk or serving extras")
     ap.add_argument("--codec", action="store_true", help="with --quick: still measure the track-model codec")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="run the automatic knob setting instead of the tuned one")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2502_09138_amd", "tuning_gfx950.json"),
+                    help="tuning table (knob setting per shape class); a class not in it is tuned on the spot")
+    ap.add_argument("--knobs", default="", help='explicit knob setting as JSON, e.g. {"link_slots": 4}')
     ap.add_argument("--codec-q", default="0.01,0.015", help="residual quanta q_y,q_z (cm) of the codec")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -363,6 +371,23 @@ def main():
     z = torch.from_numpy(ev.z).to(dev)
     torch.cuda.synchronize()
     tr = Tracker(default_config(), max_clusters=N, max_sectors=ev.n_sectors, tracklet_schedule=args.schedule)
+    tuning = None
+    if args.knobs:
+        knobs = json.loads(args.knobs)
+        tr.set_knobs(**knobs)
+        tuning = {"knobs": knobs, "source": "--knobs"}
+    elif args.tune and args.mode == "batched" and args.schedule == 0:
+        # the knob setting of this frame's shape class: from the shipped tuning table, else tuned here
+        # (outside the timed region); the steps below run it
+        t0 = time.perf_counter()
+        tuner = batching.ScheduleTuner(tr, repeats=2, cache_path=args.tune_cache if os.path.exists(args.tune_cache)
+                                       else None)
+        cached = tuner.key(ev.row_offsets) in tuner.cache
+        knobs = tuner.choose(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+        tuning = {"knobs": knobs, "source": "tuning table" if cached else "tuned", "runs": tuner.tuned_runs,
+                  "seconds": round(time.perf_counter() - t0, 3),
+                  "ms_by_setting": {k[1]: round(v, 4) for k, v in tuner.timings.items()}}
+        log(f"bench: knobs {knobs} ({tuning['source']}, {tuner.tuned_runs} runs)")
     tr.set_timing(True)   # every pass during warm-up, to find the dominant one
 
     if args.calib_copy_mb:
@@ -442,8 +467,10 @@ def main():
     value = N * args.steps / elapsed
     pass_ms = {k: float(np.mean(v)) for k, v in bd_acc.items()}
     pass_ms[dominant] = dom_ms   # the dominant pass as timed inside the timed loop
-    k5_name = "k_tracklets_rs (K5, C5)" if tr_schedule_rowsync(args.schedule, ev) else "k_seed, k_up, k_sort, k_down, k_guard (K5, C5)"
-    prof = stored_profile(wl["workload"])
+    sched = tuning["knobs"]["schedule"] if tuning else args.schedule
+    k5_name = ("k_tracklets_rs (K5, C5)" if tr_schedule_rowsync(sched, ev)
+               else "k_seed, k_up, k_sort, k_down, k_guard (K5, C5)")
+    prof = stored_profile(wl["workload"], tuning["knobs"] if tuning else None)
 
     def roof_entry(kernel, pass_name, alg_bytes, issue_bound):
         ms = pass_ms[pass_name]
@@ -489,7 +516,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": dict(wl, n_clusters=N, n_sectors=ev.n_sectors, n_rows=152, tracklets=counts["n_tracklets"],
-                       tracks=counts["n_tracks"], tracklet_schedule=args.schedule, mode=args.mode),
+                       tracks=counts["n_tracks"], tracklet_schedule=args.schedule, mode=args.mode,
+                       knobs=tuning["knobs"] if tuning else "automatic"),
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 4),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 4)},
         "e2e_host_copy": {"value": round(N * n_e2e / e2e, 1), "unit": "clusters/s",
@@ -498,6 +526,7 @@ def main():
         "passes_note": (f"{dominant}: HIP events on the tracker stream over the {args.steps} timed steps; "
                         f"other passes: {n_bd} further steps with every pass timed"),
         "dominant_pass": dominant,
+        "tuning": tuning,
         "roofline": roof.get(dominant, roof["tracklets"]),
         "roofline_passes": roof,
     }

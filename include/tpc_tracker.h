@@ -430,7 +430,7 @@ tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule);
  *   TPC_KNOB_TRACKLET_SCHEDULE  0 auto, 1 lane-per-tracklet pipeline, 2
  *                               row-synchronous (as tpc_set_tracklet_schedule)
  *   TPC_KNOB_SELECT_TILE_ROWS   0 auto (4 rows, fewer where a block would need
- *                               more than 16 KB of LDS); 1, 2, 4: rows per C6
+ *                               more than 48 KB of LDS); 1, 2, 4: rows per C6
  *                               selector tile, reduced to the largest power of
  *                               two whose blocks fit 48 KB of LDS (none: the
  *                               global-memory selector); -1: the global-memory
@@ -438,8 +438,11 @@ tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule);
  *   TPC_KNOB_REFIT_ORDER        0 the lane-per-tracklet pipeline refits in
  *                               (sector, outermost row) order, 1 in tracklet
  *                               order
+ *   TPC_KNOB_LINK_SLOTS         0 auto (8), 4 or 8: C2 up-row candidates held
+ *                               per hit before the pair search falls back to
+ *                               rescanning the window
  * TPC_E_INVAL for an unknown knob or value, or while a request is in flight. */
-enum { TPC_KNOB_TRACKLET_SCHEDULE = 1, TPC_KNOB_SELECT_TILE_ROWS = 2, TPC_KNOB_REFIT_ORDER = 3 };
+enum { TPC_KNOB_TRACKLET_SCHEDULE = 1, TPC_KNOB_SELECT_TILE_ROWS = 2, TPC_KNOB_REFIT_ORDER = 3, TPC_KNOB_LINK_SLOTS = 4 };
 tpc_status tpc_set_knob(tpc_tracker* t, int32_t knob, int32_t value);
 
 /* Per-pass timing with HIP events on the tracker's stream, for later requests.

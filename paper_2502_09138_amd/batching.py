@@ -86,25 +86,37 @@ def shape_class(row_offsets, n_rows=N_ROWS):
     return (b(S), b(mx), b(mean))
 
 
-def knob_grid(schedules=(1, 2), tile_rows=(0, 2, 4, -1), refit_orders=(0, 1)):
-    """Every knob setting to sweep: the refit order matters only for the lane-per-tracklet schedule."""
-    out = []
-    for s in schedules:
-        for r in tile_rows:
-            for o in (refit_orders if s == 1 else (0,)):
-                out.append({"schedule": s, "select_tile_rows": r, "refit_order": o})
+# Values of each tuning knob (Tracker.set_knobs), the automatic setting first.
+KNOB_SPACE = {"schedule": (1, 2), "select_tile_rows": (0, 2, 4, -1), "refit_order": (0, 1), "link_slots": (8, 4)}
+
+
+def knob_grid(space=None):
+    """Every combination of the knob values (the refit order only for the lane-per-tracklet schedule)."""
+    space = dict(KNOB_SPACE if space is None else space)
+    out = [{}]
+    for name, values in space.items():
+        nxt = []
+        for c in out:
+            for v in values:
+                if name == "refit_order" and c.get("schedule") == 2 and v != values[0]:
+                    continue
+                nxt.append(dict(c, **{name: v}))
+        out = nxt
     return out
 
 
 class ScheduleTuner:
-    """Chooses the tracker's knobs per (architecture, shape class) by timing every candidate setting on
-    the first frame of the class (all passes, HIP events, best of ``repeats``); the choice is cached,
-    optionally in a JSON file.  Candidates are knob dicts (see ``Tracker.set_knobs``) or plain schedule
-    numbers."""
+    """Chooses the tracker's knobs per (architecture, shape class) on the first frame of the class and
+    caches the choice, optionally in a JSON file.  With ``candidates`` (knob dicts or plain schedule
+    numbers) every candidate is timed; without, the knobs of ``space`` are tuned one at a time, each over
+    its values with the others at their best so far (every setting timed once at most).  A setting's
+    time is the sum of all passes (HIP events), best of ``repeats``."""
 
-    def __init__(self, tracker, candidates=(1, 2), repeats=2, cache_path=None, arch=None):
+    def __init__(self, tracker, candidates=None, repeats=2, cache_path=None, arch=None, space=None):
         self.tracker = tracker
-        self.candidates = tuple(c if isinstance(c, dict) else {"schedule": int(c)} for c in candidates)
+        self.candidates = None if candidates is None else \
+            tuple(c if isinstance(c, dict) else {"schedule": int(c)} for c in candidates)
+        self.space = dict(KNOB_SPACE if space is None else space)
         self.repeats = repeats
         self.cache_path = cache_path
         self.arch = arch or "gfx950"
@@ -118,26 +130,35 @@ class ScheduleTuner:
     def key(self, row_offsets):
         return (self.arch,) + shape_class(row_offsets)
 
+    def _time(self, key, knobs, frame):
+        tag = json.dumps(knobs, sort_keys=True)
+        if (key, tag) not in self.timings:
+            tr = self.tracker
+            tr.set_knobs(**knobs)
+            ms = float("inf")
+            for _ in range(self.repeats):
+                rid = tr.submit(*frame)
+                tr.get_device(rid)
+                ms = min(ms, sum(tr.pass_times().values()))
+                tr.release(rid)
+                self.tuned_runs += 1
+            self.timings[(key, tag)] = ms
+        return self.timings[(key, tag)]
+
     def choose(self, y, z, row_offsets, z_lo, z_hi):
         """The best knob setting for this frame's shape class (applied to the tracker); with plain
         schedule candidates, the schedule number."""
         key = self.key(row_offsets)
+        frame = (y, z, row_offsets, z_lo, z_hi)
         if key not in self.cache:
             tr = self.tracker
-            best, best_ms = None, float("inf")
             tr.set_timing(True)
-            for cand in self.candidates:
-                tr.set_knobs(**cand)
-                ms = float("inf")
-                for _ in range(self.repeats):
-                    rid = tr.submit(y, z, row_offsets, z_lo, z_hi)
-                    tr.get_device(rid)
-                    ms = min(ms, sum(tr.pass_times().values()))
-                    tr.release(rid)
-                    self.tuned_runs += 1
-                self.timings[(key, json.dumps(cand, sort_keys=True))] = ms
-                if ms < best_ms:
-                    best, best_ms = cand, ms
+            if self.candidates is not None:
+                best = min(self.candidates, key=lambda c: self._time(key, c, frame))
+            else:
+                best = {k: v[0] for k, v in self.space.items()}
+                for name, values in self.space.items():
+                    best = min((dict(best, **{name: v}) for v in values), key=lambda c: self._time(key, c, frame))
             tr.set_timing(False)
             self.cache[key] = best
             if self.cache_path:

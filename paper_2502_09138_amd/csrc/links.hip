@@ -66,10 +66,11 @@ __device__ __forceinline__ void for_window(const RowView& v, float y, float z, f
 
 // Candidate slots per lane for the passing hits of row r+1 (mean 1.6, max 7
 // on a central event), held in registers; a hit with more falls back to
-// rescanning the window.
-constexpr int kUpSlots = 8;
-
+// rescanning the window.  Two instances: 8 slots (dense frames, where more
+// slots avoid rescans) and 4 (sparse frames: leaner code and six waves per
+// SIMD instead of five); the tuning knob TPC_KNOB_LINK_SLOTS chooses.
 // Links of one hit (sorted position p, coordinates h) of row rc between rows dn and up.
+template <int kUpSlots>
 __device__ __forceinline__ void link_hit(const DevPtrs& d, uint32_t p, float2 h, const RowView& dn, const RowView& up,
                                          const RowConst& rc, float rho) {
 #pragma clang fp contract(off)
@@ -173,6 +174,7 @@ __device__ __forceinline__ RowView adjacent_view(const DevPtrs& d, uint32_t sr, 
   return v;
 }
 
+template <int kUpSlots>
 __global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho) {
   __shared__ float2 lyz[2][kSliceHits];
   __shared__ uint32_t lbs[2][kSliceBins];
@@ -199,14 +201,17 @@ __global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho) {
   const RowView dn = adjacent_view(d, sr - 1, zmin, zmax, rc.wz_dn, stage, lyz[0], lbs[0]);
   const RowView up = adjacent_view(d, sr + 1, zmin, zmax, rc.wz_up, stage, lyz[1], lbs[1]);
   __syncthreads();
-  if (mine) link_hit(d, p, h, dn, up, rc, rho);
+  if (mine) link_hit<kUpSlots>(d, p, h, dn, up, rc, rho);
 }
 
 }  // namespace
 
 void launch_links(const DevPtrs& d, uint32_t, hipStream_t s) {
   if (d.n_link_tiles == 0) return;
-  hipLaunchKernelGGL(k_links, dim3(d.n_link_tiles), dim3(kThreads), 0, s, d, d.rho);
+  if (d.k2_slots == 4)
+    hipLaunchKernelGGL(k_links<4>, dim3(d.n_link_tiles), dim3(kThreads), 0, s, d, d.rho);
+  else
+    hipLaunchKernelGGL(k_links<8>, dim3(d.n_link_tiles), dim3(kThreads), 0, s, d, d.rho);
 }
 
 }  // namespace tpc

@@ -112,6 +112,7 @@ struct DevPtrs {
   float rho;                 // (sigma_y / sigma_z)^2, float32
   int32_t k5_mode;           // 0 auto, 1 lane-per-tracklet pipeline, 2 row-synchronous
   int32_t k5_refit_order;    // 0 (sector, outermost row) buckets, 1 tracklet order
+  int32_t k2_slots;          // K2 up-candidate slots per lane: 4 or 8 (0 = 8)
   uint32_t S, R, SR, N;
   uint32_t tcap;
   uint32_t tile_cap;         // LDS words of one selector tile (max hits in a sector's row block)

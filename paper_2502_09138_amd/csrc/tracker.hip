@@ -48,7 +48,6 @@ constexpr uint64_t kScratchBytes = TPC_SCRATCH_BYTES;
 constexpr int kMaxDevices = 64;
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kSelectTileWords = 12288;     // 48 KB of LDS per selector tile at most
-constexpr uint32_t kSelectTilePreferred = 4096;  // 16 KB: multi-row tiles above this keep too few tiles resident
 constexpr uint32_t kSelectGlobal = 0xFFFFFFFFu;  // TPC_KNOB_SELECT_TILE_ROWS = -1: the global-memory selector
 
 struct Layout {   // byte offsets of every workspace buffer
@@ -632,14 +631,13 @@ tpc_status enqueue(tpc_tracker* t, const tpc_timeframe* f, uint32_t max_row, uin
   // row offsets, tile offsets and sector constants in one copy
   HIP_TRY(hipMemcpyAsync((void*)d.row_off, t->h_frame, t->lay.secs + S * sizeof(SectorConst) - t->lay.row_off,
                          hipMemcpyHostToDevice, st));
-  // selector tile: 4 rows, or 2 when a 4-row block would need more than
-  // kSelectTilePreferred words of LDS (fewer resident tiles), or 1 row up to
-  // kSelectTileWords; 0 = rows too large, global-memory selector.  (Measured:
-  // central event 4 rows 0.126 ms vs 8 rows 0.163 ms; 32-orbit frame 2 rows
-  // 1.02 ms vs 4 rows 1.25 ms.)  Per-tile owned counts are bytes, so tiles
-  // need at most 255 rows per sector.
-  // A forced tile size (TPC_KNOB_SELECT_TILE_ROWS) starts from the requested
-  // rows and allows the whole kSelectTileWords to every size.
+  // selector tile: 4 rows, or 2 or 1 where a block of 4 rows would need more
+  // than kSelectTileWords words of LDS; 0 = rows too large, global-memory
+  // selector.  (Measured with the batched selector loads: 4 rows up to 48 KB
+  // of LDS beat the earlier 16 KB limit for multi-row tiles on every workload
+  // -- time frame 3.98 against 4.14 ms per frame, central event 1.026 against
+  // 1.032 ms, chunks 11.11 against 11.45 ms.)  Per-tile owned counts are
+  // bytes, so tiles need at most 255 rows per sector.
   uint32_t tile_rows = 0, tile_cap = 0;
   const uint32_t forced = t->select_tile_rows == kSelectGlobal ? 0u : t->select_tile_rows;
   for (uint32_t tr = forced ? forced : 4; tr >= 1 && tile_rows == 0 && R <= 255 && t->select_tile_rows != kSelectGlobal;
@@ -650,7 +648,7 @@ tpc_status enqueue(tpc_tracker* t, const tpc_timeframe* f, uint32_t max_row, uin
         const uint32_t rb = std::min(R, ra + tr);
         mx = std::max(mx, f->row_offsets[s * R + rb] - f->row_offsets[s * R + ra]);
       }
-    if (mx <= (tr == 1 || forced ? kSelectTileWords : kSelectTilePreferred)) {
+    if (mx <= kSelectTileWords) {
       tile_rows = tr;
       tile_cap = std::max(mx, 1u);
     }
@@ -1082,6 +1080,10 @@ tpc_status tpc_set_knob(tpc_tracker* t, int32_t knob, int32_t value) {
     case TPC_KNOB_REFIT_ORDER:
       if (value != 0 && value != 1) return fail(TPC_E_INVAL, "refit order must be 0 or 1");
       t->d.k5_refit_order = value;
+      return TPC_OK;
+    case TPC_KNOB_LINK_SLOTS:
+      if (value != 0 && value != 4 && value != 8) return fail(TPC_E_INVAL, "link slots must be 0, 4 or 8");
+      t->d.k2_slots = value;
       return TPC_OK;
     default:
       return fail(TPC_E_INVAL, "unknown knob");

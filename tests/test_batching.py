@@ -87,13 +87,13 @@ def test_schedule_tuner_caches_per_shape_class(tmp_path):
     tr = Tracker(default_config(), max_clusters=ev.n_clusters, max_sectors=ev.n_sectors)
     try:
         path = str(tmp_path / "tune.json")
-        tuner = batching.ScheduleTuner(tr, cache_path=path)
+        tuner = batching.ScheduleTuner(tr, candidates=(1, 2), cache_path=path)
         c1 = tuner.choose(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
         runs = tuner.tuned_runs
         assert c1 in (1, 2) and runs == 4
         c2 = tuner.choose(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
         assert c2 == c1 and tuner.tuned_runs == runs          # cached: no re-timing
-        again = batching.ScheduleTuner(tr, cache_path=path)    # persisted per (arch, shape class)
+        again = batching.ScheduleTuner(tr, candidates=(1, 2), cache_path=path)    # persisted per (arch, shape class)
         assert again.choose(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi) == c1 and again.tuned_runs == 0
         out = tr.track(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
         assert out.n_tracks > 100 and out.error_flags == 0
@@ -154,5 +154,12 @@ def test_knob_tuner_sweeps_the_grid_once_per_shape_class(tmp_path):
         assert choice in grid and tuner.tuned_runs == len(grid)
         assert tuner.choose(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi) == choice
         assert tuner.tuned_runs == len(grid)
+        # one knob at a time: every value of each knob once, the others at their best so far
+        coord = batching.ScheduleTuner(tr, repeats=1)
+        c = coord.choose(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+        space = batching.KNOB_SPACE
+        print("coordinate choice", c, "runs", coord.tuned_runs, flush=True)
+        assert set(c) == set(space) and all(c[k] in v for k, v in space.items())
+        assert coord.tuned_runs == 1 + sum(len(v) - 1 for v in space.values())
     finally:
         tr.close()
