@@ -50,12 +50,13 @@ PROFILE_SOURCES = (
 )
 PROFILES = {
     "time_frame": {
-        "digests": ("cde902349f5835a0e2fe6c7547872a39958995e6", "ad6bcd87cc9f7c3f0839ae36deca241dbd83786b",
+        "digests": ("06ee634648debd71a1781a7a37f46d1b444b78e0", "7eaa7476b25eb2cd6a8b07982fccfe92b25a6537",
                     "8d4ffb5e64cc1810222dbe0c811aa511ffde5df6", "b4b103e57db5db269528a9bdae40217f2bb52ff1",
-                    "bf309c15529ec6d7132f1661f16c555d731ea38f"),
-        # tracklets: k_seed + k_up + k_sort + k_down + k_guard; VALU of k_up and k_down (the rest is < 5%)
-        "traffic_bytes": {"tracklets": 7_220_910_000, "grid": 294_330_000, "neighbours": 473_960_000},
-        "valu_insts": {"tracklets": 948_118_308, "grid": 19_770_947, "neighbours": 310_520_732},
+                    "1ced84520a9aeb9d6d180dedb987cda2122413e4"),
+        "knobs": {"schedule": 1, "select_tile_rows": 4, "refit_order": 1, "link_slots": 4},
+        # tracklets: k_seed + k_up + k_down + k_guard; VALU of k_up and k_down (the rest is < 5%)
+        "traffic_bytes": {"tracklets": 7_271_960_000, "grid": 294_500_000, "neighbours": 473_910_000},
+        "valu_insts": {"tracklets": 1_105_591_020, "grid": 19_770_947, "neighbours": 246_557_751},
         "files": "profiles/time_frame_hbm_traffic.md, profiles/time_frame_sq_counters.md",
     },
 }
