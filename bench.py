@@ -582,8 +582,10 @@ def main():
                                 "ms_per_step": round(1e3 * float(np.mean(tc)), 4), "n_clusters": evc.n_clusters,
                                 "n_chunks": evc.n_sectors, "tracks": cc["n_tracks"],
                                 "note": "512 sector-sized chunks of log-uniform occupancy (1k-200k), one batched request"}
-        # the knob tuner on this shape class, then the tuned setting timed like the default one
-        tuner = batching.ScheduleTuner(trc, candidates=batching.knob_grid(), repeats=1)
+        # the tuned knob setting of this shape class (tuning table, else tuned here), timed like the
+        # automatic one
+        tuner = batching.ScheduleTuner(trc, repeats=2, cache_path=args.tune_cache if os.path.exists(args.tune_cache)
+                                       else None)
         choice = tuner.choose(yc, zc, evc.row_offsets, evc.sector_z_lo, evc.sector_z_hi)
         tt = []
         for _ in range(5):
@@ -593,7 +595,8 @@ def main():
             trc.release(rid)
             tt.append(time.perf_counter() - s0)
         rec["uneven_chunks"]["tuned"] = {"knobs": choice, "ms_per_step": round(1e3 * float(np.mean(tt)), 4),
-                                         "tuning_runs": tuner.tuned_runs}
+                                         "tuning_runs": tuner.tuned_runs,
+                                         "source": "tuning table" if tuner.tuned_runs == 0 else "tuned"}
         # the plain path: one request per chunk, back to back
         trc.set_knobs(schedule=0, select_tile_rows=0, refit_order=0)
         pc = []
