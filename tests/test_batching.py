@@ -163,3 +163,23 @@ def test_knob_tuner_sweeps_the_grid_once_per_shape_class(tmp_path):
         assert coord.tuned_runs == 1 + sum(len(v) - 1 for v in space.values())
     finally:
         tr.close()
+
+
+@pytest.mark.gpu
+def test_knobs_reject_unknown_values():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_09138_amd.tracker import Tracker, TrackerError, TPC_E_INVAL
+    tr = Tracker(default_config(), max_clusters=1000, max_sectors=1)
+    try:
+        for knobs in ({"schedule": 3}, {"select_tile_rows": 3}, {"select_tile_rows": 8}, {"refit_order": 2},
+                      {"link_slots": 6}):
+            with pytest.raises(TrackerError) as e:
+                tr.set_knobs(**knobs)
+            assert e.value.status == TPC_E_INVAL, knobs
+        with pytest.raises(ValueError):
+            tr.set_knobs(waves=4)
+        tr.set_knobs(schedule=0, select_tile_rows=-1, refit_order=1, link_slots=4)   # all accepted
+    finally:
+        tr.close()

@@ -101,3 +101,26 @@ def test_codec_frame_without_tracks(torch_cuda):
     print("case: one sector of scattered clusters N=", ev.n_clusters, flush=True)
     c = _run(ev, 0.01, 0.01, "no tracks")
     assert c["n_tracks"] == 0 and c["n_unassigned"] == ev.n_clusters
+
+
+def test_codec_rejects_bad_arguments(torch_cuda):
+    from paper_2502_09138_amd.tracker import Tracker, TrackerError, TPC_E_INVAL
+    ev = synth.single_sector(seed=1, n_tracks=20)
+    tr = Tracker(default_config(), max_clusters=ev.n_clusters, max_sectors=1)
+    rid = tr.submit(ev.y, ev.z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi, host=True)
+    try:
+        tr.get(rid)
+        for q in (0.0, -0.01, float("nan"), float("inf")):
+            with pytest.raises(TrackerError) as e:
+                tr.encode(rid, q, 0.01)
+            assert e.value.status == TPC_E_INVAL
+        with pytest.raises(TrackerError) as e:
+            tr.encode(rid + 1, 0.01, 0.01)      # not the request in flight
+        assert e.value.status == TPC_E_INVAL
+        stream, counts = tr.encode(rid, 0.01, 0.01)
+        with pytest.raises(TrackerError) as e:
+            tr.decode(stream, counts, 0.0, 0.01)
+        assert e.value.status == TPC_E_INVAL
+    finally:
+        tr.release(rid)
+        tr.close()
