@@ -562,10 +562,20 @@ __device__ __forceinline__ uint32_t get_word(const DevPtrs& d, int w, uint32_t i
   return reinterpret_cast<const uint32_t*>(d.tk_cov)[(size_t)w * d.tcap + i];
 }
 
+__device__ __forceinline__ void set_priority(uint32_t rows_left, uint32_t& level) {
+  const uint32_t want = (rows_left >= 75) + (rows_left >= 150) + (rows_left >= 225);
+  if (want == level) return;
+  level = want;
+  if (want == 3) __builtin_amdgcn_s_setprio(3);
+  else if (want == 2) __builtin_amdgcn_s_setprio(2);
+  else if (want == 1) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
 // Chain fit and outward extension of tracklet i (seeded); false if the chain
 // fit fails, else the hand-off is written and key is its refit bucket.
 __device__ __forceinline__ bool up_one(const DevPtrs& d, const KfConst& k, const RowK* lrows, uint32_t i,
-                                       uint32_t& key, uint32_t& steps) {
+                                       uint32_t& key, uint32_t& steps, uint32_t& prio) {
   const uint32_t R = d.R, T = d.tcap;
   const uint32_t sr0 = d.start_sr[i];
   const uint32_t sec = sr0 / R, srb = sec * R, r0 = sr0 - srb;
@@ -591,6 +601,9 @@ __device__ __forceinline__ bool up_one(const DevPtrs& d, const KfConst& k, const
   int32_t hk2 = r0 + 2 <= rl ? H[(size_t)(r0 + 2) * T] : -1;
   uint2 mnx = r0 + 1 < R && r0 + 1 > rl ? d.row_meta[srb + r0 + 1] : make_uint2(0u, 0u);
   for (uint32_t r = r0 + 1; r < R; ++r) {
+    // issue priority by the rows still ahead (outward, then about as many inward): a wave far from its
+    // end goes first, so fewer waves are left running alone at the end (-1.6% on the 32-orbit frame)
+    set_priority(2 * (R - __builtin_amdgcn_readfirstlane(r)), prio);
     const bool chain = r <= rl;
     const float2 hc = hnx;
     const uint2 meta = mnx;
@@ -652,12 +665,12 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
   const XcdSched sch = xcd_sched(nt);
   if (sch.first >= sch.end) return;   // the grid is sized for the tracklet capacity
   load_rows(d, lrows);
-  uint32_t steps = 0;
+  uint32_t steps = 0, prio = 0;
   for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
     const uint32_t i = vb * kThreads + threadIdx.x;
     bool on = i < nt && d.tk_info[i] >= 0;
     uint32_t key = 0;
-    if (on) on = up_one(d, k, lrows, i, key, steps);
+    if (on) on = up_one(d, k, lrows, i, key, steps, prio);
     (void)wave_claim(d.row_nstart, key, on);   // count the tracklet in its refit bucket
   }
   uint32_t sum = steps;
@@ -700,7 +713,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
   const XcdSched sch = xcd_sched(nv);
   if (sch.first >= sch.end) return;   // the grid is sized for the tracklet capacity
   load_rows(d, lrows);
-  uint32_t steps = 0;
+  uint32_t steps = 0, prio = 0;
   for (uint32_t vb = sch.first; vb < sch.end; vb += sch.stride) {
     const uint32_t j = vb * kThreads + threadIdx.x;
     if (j >= nv || (!sorted && d.tk_info[j] < 0)) continue;
@@ -735,6 +748,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     float2 vA = hA >= 0 ? d.syz[hA] : make_float2(0.0f, 0.0f);
     uint2 mA = rout >= 1 ? d.row_meta[srb + rout - 1] : make_uint2(0u, 0u);
     for (int r = (int)rout - 1; r >= 0; --r) {
+      set_priority(2 * (uint32_t)__builtin_amdgcn_readfirstlane(r), prio);
       const int32_t hk = hA;
       const float2 vk = vA;
       const uint2 meta = mA;
@@ -849,15 +863,6 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 // Issue priority of a wave from the rows it still has to step through (a
 // longest-remaining-first order for the waves that share a SIMD); `level`
 // holds the wave's current setting, so the instruction is issued on changes only.
-__device__ __forceinline__ void set_priority(uint32_t rows_left, uint32_t& level) {
-  const uint32_t want = (rows_left >= 75) + (rows_left >= 150) + (rows_left >= 225);
-  if (want == level) return;
-  level = want;
-  if (want == 3) __builtin_amdgcn_s_setprio(3);
-  else if (want == 2) __builtin_amdgcn_s_setprio(2);
-  else if (want == 1) __builtin_amdgcn_s_setprio(1);
-  else __builtin_amdgcn_s_setprio(0);
-}
 __device__ __forceinline__ float uniform_f(float v) {
   return __int_as_float((int)__builtin_amdgcn_readfirstlane((uint32_t)__float_as_int(v)));
 }
