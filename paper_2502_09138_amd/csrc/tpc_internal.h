@@ -50,7 +50,7 @@ struct ResultHeader {
   uint64_t n_track_clusters;
   uint64_t n_steps;        // row steps taken by all tracklet lanes (C5 work measure)
   uint32_t codec_escaped;  // clusters the last C10 encoding stored raw
-  uint32_t pad1;
+  uint32_t codec_unassigned;  // clusters on no track in the last C10 encoding (host copy of the scan total)
 };
 
 // All device pointers of one request.

@@ -557,7 +557,7 @@ __global__ void k_begin(ResultHeader* h) {
   h->n_tracks = 0;
   h->pad0 = 0;
   h->codec_escaped = 0;
-  h->pad1 = 0;
+  h->codec_unassigned = 0;
   h->n_track_clusters = 0;
   h->n_steps = 0;
 }
@@ -973,12 +973,12 @@ tpc_status tpc_encode_tracks(tpc_tracker* t, uint64_t request_id, float q_y, flo
   HIP_TRY(hipGetLastError());
   uint32_t* cnt = reinterpret_cast<uint32_t*>(&t->h_hdr->codec_escaped);
   HIP_TRY(hipMemcpyAsync(cnt, a.n_escaped, 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(&t->h_hdr->pad1, a.row_pos + a.SR, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&t->h_hdr->codec_unassigned, a.row_pos + a.SR, 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   counts->n_tracks = a.n_tracks;
   counts->n_track_clusters = a.n_cl;
   counts->n_escaped = t->h_hdr->codec_escaped;
-  counts->n_unassigned = a.SR ? t->h_hdr->pad1 : 0;
+  counts->n_unassigned = a.SR ? t->h_hdr->codec_unassigned : 0;
   return TPC_OK;
 }
 
