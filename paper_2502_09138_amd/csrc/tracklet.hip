@@ -765,7 +765,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
       int32_t h = hk;
       float2 hm = vk;
       if (h < 0) h = search_m(d, meta, rk, sc, t, k, zref, hm);
-      H[(size_t)r * T] = h;
+      // the row's entry changes only where the refit searched: below the start
+      // row (never written before) or in a gap the outward pass left
+      if (below || h != hk) H[(size_t)r * T] = h;
       if (h >= 0) {
         update(t, hm.x, hm.y - zref, k, chi2);
         ++nh;
@@ -1094,7 +1096,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
           h = (kAllFit || st.fits) ? search_lds(yz_s, bs_s + st.boff, st.first, st.meta, rk, sc, t, k, zref, half)
                                    : search(d, srb + (uint32_t)rr, rk, sc, t, k, zref, unused);
         }
-        if (go) H[(size_t)rr * T] = h;
+        if (go && (below || h != hrow)) H[(size_t)rr * T] = h;   // changed only where the refit searched
         if (go && h >= 0) {
           const float2 hm = (kAllFit || st.fits) ? yz_s[(uint32_t)h - st.first] : d.syz[h];
           update(t, hm.x, hm.y - zref, k, chi2);
