@@ -88,6 +88,8 @@ struct DevPtrs {
   float* tk_chi2;            // [Tcap]
   uint32_t* k5_off;          // [SR+1] lane-per-tracklet K5: refit bucket offsets (sector, outermost row)
   uint32_t* k5_perm;         // [Tcap] tracklets in bucket order
+  uint32_t* k5_inv;          // [Tcap] bucket slot of each tracklet
+  uint32_t* k5_rec;          // [25 * Tcap] refit results in slot order (one record per tracklet)
   // C6
   uint32_t* W;               // [N] ownership word (32-bit key) per sorted position
   uint8_t* own_part;         // [R * Tcap] owned hits of a tracklet per selector tile (then prefixes)

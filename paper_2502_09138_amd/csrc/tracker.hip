@@ -52,7 +52,7 @@ constexpr uint32_t kSelectGlobal = 0xFFFFFFFFu;  // TPC_KNOB_SELECT_TILE_ROWS = 
 
 struct Layout {   // byte offsets of every workspace buffer
   uint64_t row_off, rows, secs, row_dims, row_meta, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
-      row_start_off, start_pos, start_sr, wave_off, tile_off, tile_sr, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, k5_off, k5_perm, W, own_part, tk_pack,
+      row_start_off, start_pos, start_sr, wave_off, tile_off, tile_sr, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, k5_off, k5_perm, k5_inv, k5_rec, W, own_part, tk_pack,
       tk_scan, acc_list,
       out_sector, out_start, out_first, out_clusters, out_xref, out_param, out_cov, out_chi2, out_ndf, scan_blocks,
       hdr, in_y, in_z, m_phys, m_nbr, m_sec_first, m_succ, m_pred_key, m_next, m_has_pred, m_head_flag, m_head_scan,
@@ -113,6 +113,8 @@ Layout layout_of(const Caps& k) {
   L.tk_chi2 = take(k.T * 4);
   L.k5_off = take((k.SRmax + 1) * 4);
   L.k5_perm = take(k.T * 4);
+  L.k5_inv = take(k.T * 4);
+  L.k5_rec = take(k.T * 25 * 4);
   L.W = take(k.N * 4);
   L.own_part = take((uint64_t)k.R * k.T);
   L.tk_pack = take(k.T * 8);
@@ -286,6 +288,8 @@ void carve(tpc_tracker* t) {
   d.tk_chi2 = (float*)(w + lay.tk_chi2);
   d.k5_off = (uint32_t*)(w + lay.k5_off);
   d.k5_perm = (uint32_t*)(w + lay.k5_perm);
+  d.k5_inv = (uint32_t*)(w + lay.k5_inv);
+  d.k5_rec = (uint32_t*)(w + lay.k5_rec);
   d.W = (uint32_t*)(w + lay.W);
   d.own_part = (uint8_t*)(w + lay.own_part);
   d.tk_pack = (unsigned long long*)(w + lay.tk_pack);

@@ -444,17 +444,43 @@ __device__ __forceinline__ void store_tracklet(const DevPtrs& d, uint32_t i, int
 
 // The covariance guard over every stored tracklet, one lane each (for k_down,
 // whose lanes store as they finish: there the guard would cost the whole wave
-// once for every group of lanes that finish together).
+// once for every group of lanes that finish together).  When the refit ran in
+// bucket order its results wait in slot order (one contiguous record per
+// tracklet, see kRec*), so that the refit's lanes write whole lines; the
+// guard gathers each tracklet's record through the bucket slot of tracklet i
+// and writes the result arrays in tracklet order.
+enum : int { kRecInfo = 0, kRecParam = 4, kRecCov = 9, kRecChi2 = 24, kRecWords = 25 };
+
 __global__ void __launch_bounds__(256) k_guard(DevPtrs d) {
   const uint32_t nt = min(d.hdr->n_starts, d.tcap), T = d.tcap;
+  const bool staged = d.k5_refit_order == 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
-    if (d.tk_info[i] < 1) continue;
-    float c[15];
+    if (staged) {
+      if (d.tk_info[i] < 0) continue;   // no seed, or the chain fit failed: no refit record
+      const uint32_t* rec = d.k5_rec + (size_t)d.k5_inv[i] * kRecWords;
+      uint32_t w[kRecWords];
 #pragma unroll
-    for (int q = 0; q < 15; ++q) c[q] = d.tk_cov[(size_t)q * T + i];
-    spd_guard(c);
+      for (int q = 0; q < kRecWords; ++q) w[q] = rec[q];
 #pragma unroll
-    for (int q = 0; q < 15; ++q) d.tk_cov[(size_t)q * T + i] = c[q];
+      for (int q = 0; q < 4; ++q) d.tk_info[(size_t)q * T + i] = (int32_t)w[kRecInfo + q];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) d.tk_param[(size_t)q * T + i] = __int_as_float((int)w[kRecParam + q]);
+      float c[15];
+#pragma unroll
+      for (int q = 0; q < 15; ++q) c[q] = __int_as_float((int)w[kRecCov + q]);
+      spd_guard(c);
+#pragma unroll
+      for (int q = 0; q < 15; ++q) d.tk_cov[(size_t)q * T + i] = c[q];
+      d.tk_chi2[i] = __int_as_float((int)w[kRecChi2]);
+    } else {
+      if (d.tk_info[i] < 1) continue;
+      float c[15];
+#pragma unroll
+      for (int q = 0; q < 15; ++q) c[q] = d.tk_cov[(size_t)q * T + i];
+      spd_guard(c);
+#pragma unroll
+      for (int q = 0; q < 15; ++q) d.tk_cov[(size_t)q * T + i] = c[q];
+    }
   }
 }
 
@@ -689,7 +715,10 @@ __global__ void __launch_bounds__(256) k_sort(DevPtrs d) {
     const bool on = i < nt && d.tk_info[i] >= 0;
     const uint32_t key = on ? get_word(d, kHoSec, i) * R + get_word(d, kHoRout, i) : 0u;
     const uint32_t slot = wave_claim(d.k5_off, key, on);
-    if (on) d.k5_perm[slot] = i;
+    if (on) {
+      d.k5_perm[slot] = i;
+      d.k5_inv[i] = slot;
+    }
   }
 }
 
@@ -793,7 +822,20 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
       snap.c[4 * q + 1] = w.z;
       snap.c[4 * q + 2] = w.w;
     }
-    store_tracklet<false>(d, i, nh, rin, rout, r0, snap, chi2, zref);
+    if (sorted) {   // the record at the tracklet's bucket slot: consecutive lanes, consecutive records
+      uint32_t* rec = d.k5_rec + (size_t)j * kRecWords;
+      rec[kRecInfo] = (uint32_t)nh;
+      rec[kRecInfo + 1] = rin;
+      rec[kRecInfo + 2] = rout;
+      rec[kRecInfo + 3] = r0;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) rec[kRecParam + q] = (uint32_t)__float_as_int(q == 1 ? snap.p[q] + zref : snap.p[q]);
+#pragma unroll
+      for (int q = 0; q < 15; ++q) rec[kRecCov + q] = (uint32_t)__float_as_int(snap.c[q]);
+      rec[kRecChi2] = (uint32_t)__float_as_int(chi2);
+    } else {
+      store_tracklet<false>(d, i, nh, rin, rout, r0, snap, chi2, zref);
+    }
   }
   uint32_t sum = steps;
 #pragma unroll
