@@ -185,7 +185,9 @@ __device__ __forceinline__ bool propagate(Trk& t, float dx, const KfConst& k) {
 // Kalman update with a measurement of (y, z).  The covariance update is the
 // plain C' = C - K H C: in double it keeps far more precision than the
 // parameters need (the Joseph form, which guards the positive definiteness of
-// a float32 recursion, costs 40 more double operations per step).
+// a float32 recursion, costs 40 more double operations per step).  Each
+// element takes two fused multiply-adds (the sum of the two products and its
+// subtraction would be three operations).
 __device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst& k, float& chi2) {
   using P = par_t;
   using V = cov_t;
@@ -206,12 +208,12 @@ __device__ __forceinline__ void update(Trk& t, float ym, float zm, const KfConst
   for (int i = 0; i < 5; ++i) {
     K0[i] = c0[i] * I00 + c1[i] * I01;
     K1[i] = c0[i] * I01 + c1[i] * I11;
-    t.p[i] += P(K0[i] * r0 + K1[i] * r1);
+    t.p[i] = fma(K0[i], r0, fma(K1[i], r1, t.p[i]));
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j) c[tri(i, j)] -= K0[i] * c0[j] + K1[i] * c1[j];
+    for (int j = 0; j <= i; ++j) c[tri(i, j)] = fma(-K0[i], c0[j], fma(-K1[i], c1[j], c[tri(i, j)]));
   chi2 += float(r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1));
 }
 
