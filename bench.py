@@ -50,13 +50,13 @@ PROFILE_SOURCES = (
 )
 PROFILES = {
     "time_frame": {
-        "digests": ("94c7842a2940491446d0c4bbcf55fc6a7383917f", "7eaa7476b25eb2cd6a8b07982fccfe92b25a6537",
+        "digests": ("41cdf6fe665c598522c680df22e5548fd813eb51", "7eaa7476b25eb2cd6a8b07982fccfe92b25a6537",
                     "8d4ffb5e64cc1810222dbe0c811aa511ffde5df6", "b4b103e57db5db269528a9bdae40217f2bb52ff1",
-                    "1ced84520a9aeb9d6d180dedb987cda2122413e4"),
+                    "a55c6209ab4f4ee73656d69fb30ca16feef671f7"),
         "knobs": {"schedule": 1, "select_tile_rows": 4, "refit_order": 0, "link_slots": 4},
         # tracklets: k_seed + k_up + k_sort + k_down + k_guard; VALU of k_up and k_down (the rest is < 5%)
-        "traffic_bytes": {"tracklets": 6_598_330_000, "grid": 294_230_000, "neighbours": 473_910_000},
-        "valu_insts": {"tracklets": 987_378_495, "grid": 19_770_947, "neighbours": 246_557_751},
+        "traffic_bytes": {"tracklets": 5_278_940_000, "grid": 294_370_000, "neighbours": 473_900_000},
+        "valu_insts": {"tracklets": 956_291_127, "grid": 19_770_947, "neighbours": 246_557_751},
         "files": "profiles/time_frame_hbm_traffic.md, profiles/time_frame_sq_counters.md",
     },
 }
