@@ -50,13 +50,13 @@ PROFILE_SOURCES = (
 )
 PROFILES = {
     "time_frame": {
-        "digests": ("41cdf6fe665c598522c680df22e5548fd813eb51", "7eaa7476b25eb2cd6a8b07982fccfe92b25a6537",
+        "digests": ("41cdf6fe665c598522c680df22e5548fd813eb51", "efc08ac10bd80460be4d8dc9fad39568059661f3",
                     "8d4ffb5e64cc1810222dbe0c811aa511ffde5df6", "b4b103e57db5db269528a9bdae40217f2bb52ff1",
-                    "a55c6209ab4f4ee73656d69fb30ca16feef671f7"),
-        "knobs": {"schedule": 1, "select_tile_rows": 4, "refit_order": 0, "link_slots": 4},
+                    "9840f3423f8d77035865ae9f05e3e7f580fd4bd4"),
+        "knobs": {"schedule": 1, "select_tile_rows": 4, "refit_order": 0, "link_slots": 4, "link_group": -1},
         # tracklets: k_seed + k_up + k_sort + k_down + k_guard; VALU of k_up and k_down (the rest is < 5%)
-        "traffic_bytes": {"tracklets": 5_278_940_000, "grid": 294_370_000, "neighbours": 473_900_000},
-        "valu_insts": {"tracklets": 956_291_127, "grid": 19_770_947, "neighbours": 246_557_751},
+        "traffic_bytes": {"tracklets": 5_282_740_000, "grid": 294_330_000, "neighbours": 182_360_000},
+        "valu_insts": {"tracklets": 956_170_180, "grid": 19_770_947, "neighbours": 247_349_791},
         "files": "profiles/time_frame_hbm_traffic.md, profiles/time_frame_sq_counters.md",
     },
 }

@@ -441,8 +441,18 @@ tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule);
  *   TPC_KNOB_LINK_SLOTS         0 auto (8), 4 or 8: C2 up-row candidates held
  *                               per hit before the pair search falls back to
  *                               rescanning the window
+ *   TPC_KNOB_LINK_GROUP         0 auto (64), 1..4096: consecutive C2 tiles
+ *                               (64 hits each) given to one XCD before the
+ *                               next XCD's group (1 deals them out one by
+ *                               one); -1: one contiguous eighth per XCD
  * TPC_E_INVAL for an unknown knob or value, or while a request is in flight. */
-enum { TPC_KNOB_TRACKLET_SCHEDULE = 1, TPC_KNOB_SELECT_TILE_ROWS = 2, TPC_KNOB_REFIT_ORDER = 3, TPC_KNOB_LINK_SLOTS = 4 };
+enum {
+  TPC_KNOB_TRACKLET_SCHEDULE = 1,
+  TPC_KNOB_SELECT_TILE_ROWS = 2,
+  TPC_KNOB_REFIT_ORDER = 3,
+  TPC_KNOB_LINK_SLOTS = 4,
+  TPC_KNOB_LINK_GROUP = 5
+};
 tpc_status tpc_set_knob(tpc_tracker* t, int32_t knob, int32_t value);
 
 /* Per-pass timing with HIP events on the tracker's stream, for later requests.

@@ -87,7 +87,8 @@ def shape_class(row_offsets, n_rows=N_ROWS):
 
 
 # Values of each tuning knob (Tracker.set_knobs), the automatic setting first.
-KNOB_SPACE = {"schedule": (1, 2), "select_tile_rows": (0, 2, 4, -1), "refit_order": (0, 1), "link_slots": (8, 4)}
+KNOB_SPACE = {"schedule": (1, 2), "select_tile_rows": (0, 2, 4, -1), "refit_order": (0, 1), "link_slots": (8, 4),
+              "link_group": (64, 1, 512, -1)}
 
 
 def knob_grid(space=None):

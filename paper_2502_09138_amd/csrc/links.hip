@@ -12,6 +12,8 @@
 // All window tests and the pair deviation use float32 with contraction off, in
 // the order the definition writes them, so the argmin is bit-identical to any
 // other evaluation of the definition.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace tpc {
@@ -175,10 +177,16 @@ __device__ __forceinline__ RowView adjacent_view(const DevPtrs& d, uint32_t sr, 
 }
 
 template <int kUpSlots>
-__global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho) {
+__global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho, uint32_t G) {
   __shared__ float2 lyz[2][kSliceHits];
   __shared__ uint32_t lbs[2][kSliceBins];
-  const uint32_t tile = blockIdx.x;
+  // Tiles go to the XCDs (block b runs on XCD b % kXcds) in groups of G
+  // consecutive tiles, group g on XCD g % kXcds: the adjacent-row runs that
+  // tiles of rows r - 1 and r + 1 both stage are then read through one L2
+  // (G = 1: consecutive tiles on consecutive XCDs).
+  const uint32_t l = blockIdx.x / kXcds;
+  const uint32_t tile = G <= 1 ? blockIdx.x : ((l / G) * kXcds + blockIdx.x % kXcds) * G + l % G;
+  if (tile >= d.n_link_tiles) return;
   const uint32_t sr = d.tile_sr[tile], R = d.R, row = sr % R;
   const uint32_t a = d.row_off[sr] + (tile - d.tile_off[sr]) * kThreads;
   const uint32_t cnt = min((uint32_t)kThreads, d.row_off[sr + 1] - a);
@@ -208,10 +216,15 @@ __global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho) {
 
 void launch_links(const DevPtrs& d, uint32_t, hipStream_t s) {
   if (d.n_link_tiles == 0) return;
+  // group size: as set, or one contiguous eighth of the tiles per XCD
+  const uint32_t n = d.n_link_tiles;
+  const uint32_t G = d.k2_group == kLinkGroupEighth ? (n + kXcds - 1) / kXcds : std::max<uint32_t>(1u, d.k2_group);
+  const uint64_t groups = (n + (uint64_t)G - 1) / G;
+  const uint32_t blocks = G == 1 ? n : (uint32_t)((groups + kXcds - 1) / kXcds * kXcds * G);   // every group slot
   if (d.k2_slots == 4)
-    hipLaunchKernelGGL(k_links<4>, dim3(d.n_link_tiles), dim3(kThreads), 0, s, d, d.rho);
+    hipLaunchKernelGGL(k_links<4>, dim3(blocks), dim3(kThreads), 0, s, d, d.rho, G);
   else
-    hipLaunchKernelGGL(k_links<8>, dim3(d.n_link_tiles), dim3(kThreads), 0, s, d, d.rho);
+    hipLaunchKernelGGL(k_links<8>, dim3(blocks), dim3(kThreads), 0, s, d, d.rho, G);
 }
 
 }  // namespace tpc

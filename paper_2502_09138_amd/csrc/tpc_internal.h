@@ -10,6 +10,7 @@ constexpr float kMaxCoord = 16384.0f;   // |y|, |z| beyond this (or non-finite) 
 constexpr float kWinPad = 0.01f;    // cm added to a search window before binning (covers rounding)
 constexpr int kPasses = 6;
 constexpr uint32_t kLinkTile = 64;    // hits per K2 tile (one wave)
+constexpr uint32_t kLinkGroupEighth = 0xFFFFFFFFu;   // K2 group size: one contiguous eighth of the tiles per XCD
 
 // Per pad row: float32 constants used by C1, C2 and C5 (computed in double on the host, rounded once).
 struct RowConst {
@@ -115,6 +116,7 @@ struct DevPtrs {
   int32_t k5_mode;           // 0 auto, 1 lane-per-tracklet pipeline, 2 row-synchronous
   int32_t k5_refit_order;    // 0 (sector, outermost row) buckets, 1 tracklet order
   int32_t k2_slots;          // K2 up-candidate slots per lane: 4 or 8 (0 = 8)
+  uint32_t k2_group;         // K2 tiles per XCD group (1: round robin, kLinkGroupEighth: an eighth of the tiles)
   uint32_t S, R, SR, N;
   uint32_t tcap;
   uint32_t tile_cap;         // LDS words of one selector tile (max hits in a sector's row block)
