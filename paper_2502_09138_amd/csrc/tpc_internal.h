@@ -10,6 +10,8 @@ constexpr float kMaxCoord = 16384.0f;   // |y|, |z| beyond this (or non-finite) 
 constexpr float kWinPad = 0.01f;    // cm added to a search window before binning (covers rounding)
 constexpr int kPasses = 6;
 constexpr uint32_t kLinkTile = 64;    // hits per K2 tile (one wave)
+constexpr uint32_t kPackHits = 1024;  // K1: consecutive rows sorted by one workgroup up to this many hits
+constexpr uint32_t kPackRows = 32;    // and this many rows
 constexpr uint32_t kLinkGroupEighth = 0xFFFFFFFFu;   // K2 group size: one contiguous eighth of the tiles per XCD
 
 // Per pad row: float32 constants used by C1, C2 and C5 (computed in double on the host, rounded once).
@@ -63,6 +65,7 @@ struct DevPtrs {
   const RowConst* rows;      // [R]
   const SectorConst* secs;   // [S]
   // C1
+  const uint32_t* pack_first;   // [n_packs + 1] first (sector, row) slot of each K1 pack, then SR
   uint32_t* row_dims;        // [SR]
   uint2* row_meta;           // [SR] (bin_start offset of the row, dims) for one-load grid lookups
   uint32_t* bin_start;       // [N + 2SR]
@@ -121,6 +124,7 @@ struct DevPtrs {
   uint32_t tcap;
   uint32_t tile_cap;         // LDS words of one selector tile (max hits in a sector's row block)
   uint32_t n_link_tiles;     // K2 tiles of this request
+  uint32_t n_packs;          // K1 row packs of this request
   uint32_t max_tracks;
   uint64_t max_track_clusters;
 };
@@ -208,7 +212,7 @@ constexpr int kScanBlock = 1024;                   // elements per scan block (2
 constexpr int kScanMaxBlocks = 8192;               // supports scans of up to 8M elements
 
 // ---- launch wrappers (each in its own .hip file) ----
-void launch_grid(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
+void launch_grid(const DevPtrs& d, uint32_t max_row_hits, uint32_t max_pack_hits, hipStream_t s);
 void launch_links(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
 void launch_clean_starts(const DevPtrs& d, uint32_t max_row_hits, hipStream_t s);
 void launch_tracklets(const DevPtrs& d, const KfConst& k, uint32_t max_row_hits, hipStream_t s);

@@ -52,7 +52,7 @@ constexpr uint32_t kLinkGroupAuto = 64;          // TPC_KNOB_LINK_GROUP = 0: K2 
 constexpr uint32_t kSelectGlobal = 0xFFFFFFFFu;  // TPC_KNOB_SELECT_TILE_ROWS = -1: the global-memory selector
 
 struct Layout {   // byte offsets of every workspace buffer
-  uint64_t row_off, rows, secs, row_dims, row_meta, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
+  uint64_t row_off, rows, secs, pack_first, row_dims, row_meta, bin_start, syz, sid, up0, down0, up1, down1, sflag, row_nstart,
       row_start_off, start_pos, start_sr, wave_off, tile_off, tile_sr, tk_rowhit, tk_info, tk_param, tk_cov, tk_chi2, k5_off, k5_perm, k5_inv, k5_rec, W, own_part, tk_pack,
       tk_scan, acc_list,
       out_sector, out_start, out_first, out_clusters, out_xref, out_param, out_cov, out_chi2, out_ndf, scan_blocks,
@@ -89,6 +89,7 @@ Layout layout_of(const Caps& k) {
   L.row_off = take((k.SRmax + 1) * 4);
   L.tile_off = take((k.SRmax + 1) * 4);
   L.secs = take((uint64_t)k.Smax * sizeof(SectorConst));
+  L.pack_first = take((k.SRmax + 1) * 4);
   L.rows = take((uint64_t)k.R * sizeof(RowConst));
   L.row_dims = take(k.SRmax * 4);
   L.row_meta = take(k.SRmax * 8);
@@ -232,6 +233,7 @@ struct tpc_tracker {
   uint32_t* h_row_off = nullptr;
   uint32_t* h_tile_off = nullptr;
   SectorConst* h_secs = nullptr;
+  uint32_t* h_pack = nullptr;
   ResultHeader* h_hdr = nullptr;
   char* h_out = nullptr;      // all outputs, laid out like the device outputs
   char* h_merge = nullptr;    // merger outputs (allocated at the first merge), laid out like the device ones
@@ -265,6 +267,7 @@ void carve(tpc_tracker* t) {
   d.row_off = (const uint32_t*)(w + lay.row_off);
   d.rows = (const RowConst*)(w + lay.rows);
   d.secs = (const SectorConst*)(w + lay.secs);
+  d.pack_first = (const uint32_t*)(w + lay.pack_first);
   d.row_dims = (uint32_t*)(w + lay.row_dims);
   d.row_meta = (uint2*)(w + lay.row_meta);
   d.bin_start = (uint32_t*)(w + lay.bin_start);
@@ -319,6 +322,7 @@ void carve(tpc_tracker* t) {
     t->h_row_off = (uint32_t*)t->h_frame;
     t->h_tile_off = (uint32_t*)(t->h_frame + (lay.tile_off - lay.row_off));
     t->h_secs = (SectorConst*)(t->h_frame + (lay.secs - lay.row_off));
+    t->h_pack = (uint32_t*)(t->h_frame + (lay.pack_first - lay.row_off));
   }
 }
 
@@ -454,7 +458,7 @@ tpc_status tpc_tracker_create(const tpc_tracker_config* cfg, tpc_tracker** out) 
   k.n_rows = cfg->n_rows;
   // pinned host buffers, sized for the create-time capacities (later bindings are no larger)
   t->host_caps = caps;
-  if (hipHostMalloc((void**)&t->h_frame, lay.secs + caps.Smax * sizeof(SectorConst) - lay.row_off) != hipSuccess ||
+  if (hipHostMalloc((void**)&t->h_frame, lay.pack_first + (caps.SRmax + 1) * 4 - lay.row_off) != hipSuccess ||
       hipHostMalloc((void**)&t->h_hdr, sizeof(ResultHeader)) != hipSuccess ||
       hipHostMalloc((void**)&t->h_rows, R * sizeof(RowConst)) != hipSuccess)
     return cleanup(fail(TPC_E_NOMEM, "hipHostMalloc staging"));
@@ -634,8 +638,26 @@ tpc_status enqueue(tpc_tracker* t, const tpc_timeframe* f, uint32_t max_row, uin
     t->h_tile_off[SR] = nt;
     d.n_link_tiles = nt;
   }
-  // row offsets, tile offsets and sector constants in one copy
-  HIP_TRY(hipMemcpyAsync((void*)d.row_off, t->h_frame, t->lay.secs + S * sizeof(SectorConst) - t->lay.row_off,
+  // K1 packs: consecutive rows up to kPackHits hits and kPackRows rows (a larger row alone)
+  uint32_t max_pack = 0;
+  {
+    uint32_t np = 0, cur = 0, rows = 0;
+    for (uint32_t i = 0; i < SR; ++i) {
+      const uint32_t n = f->row_offsets[i + 1] - f->row_offsets[i];
+      if (rows && (cur + n > kPackHits || rows == kPackRows)) {
+        max_pack = std::max(max_pack, cur);
+        cur = rows = 0;
+      }
+      if (!rows) t->h_pack[np++] = i;
+      cur += n;
+      ++rows;
+    }
+    if (rows) max_pack = std::max(max_pack, cur);
+    t->h_pack[np] = SR;
+    d.n_packs = np;
+  }
+  // row offsets, tile offsets, sector constants and packs in one copy
+  HIP_TRY(hipMemcpyAsync((void*)d.row_off, t->h_frame, t->lay.pack_first + (d.n_packs + 1) * 4 - t->lay.row_off,
                          hipMemcpyHostToDevice, st));
   // selector tile: 4 rows, or 2 or 1 where a block of 4 rows would need more
   // than kSelectTileWords words of LDS; 0 = rows too large, global-memory
@@ -668,7 +690,7 @@ tpc_status enqueue(tpc_tracker* t, const tpc_timeframe* f, uint32_t max_row, uin
   };
   HIP_TRY(mark(0));
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, st, d.hdr);
-  launch_grid(d, max_row, st);
+  launch_grid(d, max_row, max_pack, st);
   HIP_TRY(mark(1));
   launch_links(d, max_row, st);
   HIP_TRY(mark(2));
