@@ -17,9 +17,16 @@ constexpr int kThreads = 256;
 // whole batch before the next level needs it.
 constexpr int kBatch = 4;
 
+// Rows go to the XCDs (block b runs on XCD b % kXcds) in groups of kRowGroup
+// consecutive rows, group g on XCD g % kXcds, so that the links of rows r - 1
+// and r + 1 that a row reads are mostly in its own XCD's L2.
+constexpr uint32_t kRowGroup = 16;
+
 __global__ void __launch_bounds__(kThreads) k_clean(DevPtrs d) {
   __shared__ uint32_t wsum[kThreads / kWave];
-  const uint32_t sr = blockIdx.x;
+  const uint32_t l = blockIdx.x / kXcds;
+  const uint32_t sr = ((l / kRowGroup) * kXcds + blockIdx.x % kXcds) * kRowGroup + l % kRowGroup;
+  if (sr >= d.SR) return;
   const uint32_t a = d.row_off[sr], n = d.row_off[sr + 1] - a;
   uint32_t cnt = 0;
   for (uint32_t j0 = threadIdx.x; j0 < n; j0 += kBatch * kThreads) {
@@ -91,7 +98,8 @@ __global__ void __launch_bounds__(kThreads) k_starts(DevPtrs d) {
 
 void launch_clean_starts(const DevPtrs& d, uint32_t, hipStream_t s) {
   if (d.SR == 0) return;
-  hipLaunchKernelGGL(k_clean, dim3(d.SR), dim3(kThreads), 0, s, d);
+  const uint32_t groups = (d.SR + kRowGroup - 1) / kRowGroup;
+  hipLaunchKernelGGL(k_clean, dim3((groups + kXcds - 1) / kXcds * kXcds * kRowGroup), dim3(kThreads), 0, s, d);
   launch_scan_u32(d.row_nstart, d.row_start_off, d.SR, d.scan_blocks, s);
   hipLaunchKernelGGL(k_starts, dim3(d.SR), dim3(kThreads), 0, s, d);
 }
