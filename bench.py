@@ -51,12 +51,12 @@ PROFILE_SOURCES = (
 PROFILES = {
     "time_frame": {
         "digests": ("41cdf6fe665c598522c680df22e5548fd813eb51", "efc08ac10bd80460be4d8dc9fad39568059661f3",
-                    "8d4ffb5e64cc1810222dbe0c811aa511ffde5df6", "b4b103e57db5db269528a9bdae40217f2bb52ff1",
-                    "9840f3423f8d77035865ae9f05e3e7f580fd4bd4"),
+                    "0c2bdc7fab0f213bed5c4784cc480462ad908377", "b4b103e57db5db269528a9bdae40217f2bb52ff1",
+                    "b3ba03b8d0b88dea4798aff54380ee4fa0a1121f"),
         "knobs": {"schedule": 1, "select_tile_rows": 4, "refit_order": 0, "link_slots": 4, "link_group": -1},
         # tracklets: k_seed + k_up + k_sort + k_down + k_guard; VALU of k_up and k_down (the rest is < 5%)
-        "traffic_bytes": {"tracklets": 5_282_740_000, "grid": 294_330_000, "neighbours": 182_360_000},
-        "valu_insts": {"tracklets": 956_170_180, "grid": 19_770_947, "neighbours": 247_349_791},
+        "traffic_bytes": {"tracklets": 5_287_460_000, "grid": 292_280_000, "neighbours": 182_360_000},
+        "valu_insts": {"tracklets": 956_153_861, "grid": 21_682_775, "neighbours": 247_349_791},
         "files": "profiles/time_frame_hbm_traffic.md, profiles/time_frame_sq_counters.md",
     },
 }

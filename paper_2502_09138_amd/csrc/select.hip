@@ -42,10 +42,20 @@ struct Tile {
   uint32_t s, ra, rb, first, n, ts, te;
 };
 
-__device__ __forceinline__ Tile tile_of(const DevPtrs& d, uint32_t tile_rows, uint32_t n_tiles) {
+// Tiles go to the XCDs (block b runs on XCD b % kXcds) in groups of half a
+// sector's tiles, group g on XCD g % kXcds: a sector's tracklet arrays, which
+// every tile of the sector scans, are then read through two L2s instead of
+// all eight.  Returns the tile (sector-major), or at least S * n_tiles for a
+// block without one.
+__device__ __forceinline__ uint32_t tile_index(const DevPtrs& d, uint32_t n_tiles) {
+  const uint32_t G = (n_tiles + 1) / 2, l = blockIdx.x / kXcds;
+  return ((l / G) * kXcds + blockIdx.x % kXcds) * G + l % G;
+}
+
+__device__ __forceinline__ Tile tile_of(const DevPtrs& d, uint32_t v, uint32_t tile_rows, uint32_t n_tiles) {
   Tile t;
-  t.s = blockIdx.x / n_tiles;
-  const uint32_t tt = blockIdx.x % n_tiles;
+  t.s = v / n_tiles;
+  const uint32_t tt = v % n_tiles;
   t.ra = tt * tile_rows;
   t.rb = min(d.R, t.ra + tile_rows);
   const uint32_t srb = t.s * d.R;
@@ -97,7 +107,9 @@ __device__ __forceinline__ void tile_hits(const DevPtrs& d, const KfConst& k, co
 
 __global__ void __launch_bounds__(kThreads) k_claim_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
   extern __shared__ uint32_t wt[];
-  const Tile tl = tile_of(d, tile_rows, n_tiles);
+  const uint32_t v = tile_index(d, n_tiles);
+  if (v >= d.S * n_tiles) return;
+  const Tile tl = tile_of(d, v, tile_rows, n_tiles);
   const uint32_t T = d.tcap;
   for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) wt[j] = 0u;
   __syncthreads();
@@ -113,7 +125,7 @@ __global__ void __launch_bounds__(kThreads) k_claim_tiles(DevPtrs d, KfConst k, 
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) d.W[tl.first + j] = wt[j];
   // every claim on the tile's rows is in: count each tracklet's owned hits here
-  const uint32_t tt = blockIdx.x % n_tiles;
+  const uint32_t tt = v % n_tiles;
   for (uint32_t i0 = tl.ts + threadIdx.x; i0 < tl.te; i0 += kBatch * kThreads) {
     TileHits th;
     tile_hits(d, k, tl, i0, th);
@@ -164,8 +176,10 @@ __global__ void __launch_bounds__(kThreads) k_accept(DevPtrs d, KfConst k, uint3
 
 __global__ void __launch_bounds__(kThreads) k_emit_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
   extern __shared__ uint32_t wt[];
-  const Tile tl = tile_of(d, tile_rows, n_tiles);
-  const uint32_t T = d.tcap, tt = blockIdx.x % n_tiles;
+  const uint32_t v = tile_index(d, n_tiles);
+  if (v >= d.S * n_tiles) return;
+  const Tile tl = tile_of(d, v, tile_rows, n_tiles);
+  const uint32_t T = d.tcap, tt = v % n_tiles;
   for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) wt[j] = d.W[tl.first + j];
   // the sector's tracks: [track index of its first tracklet, ... of the next sector's), in track order
   const uint32_t v0 = (uint32_t)(d.tk_scan[tl.ts] & 0xFFFFFFFFull);
@@ -342,7 +356,8 @@ void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipSt
   if (tile_rows > 0 && tile_rows <= (uint32_t)kTileRowsMax && d.S > 0) {
     const uint32_t n_tiles = (d.R + tile_rows - 1) / tile_rows;
     const size_t lds = (size_t)d.tile_cap * sizeof(uint32_t);
-    const dim3 tiles(d.S * n_tiles);
+    const uint32_t G = (n_tiles + 1) / 2, groups = (d.S * n_tiles + G - 1) / G;
+    const dim3 tiles((groups + kXcds - 1) / kXcds * kXcds * G);   // every group slot of every XCD
     hipLaunchKernelGGL(k_claim_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
     hipLaunchKernelGGL(k_accept, dim3(blocks), dim3(kThreads), 0, s, d, k, tile_rows);
     launch_scan_u64(d.tk_pack, d.tk_scan, &d.hdr->n_starts, d.tcap, d.scan_blocks, s);
