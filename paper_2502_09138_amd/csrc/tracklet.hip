@@ -621,12 +621,14 @@ __device__ __forceinline__ bool up_one(const DevPtrs& d, const KfConst& k, const
   uint32_t rout = rl;
   int miss = 0;
   bool failed = false;
-  // chain fit and outward extension, one row per iteration; the chain hit of
-  // the next row (its index one more row ahead) and the next row's grid word
-  // are loaded while this row is stepped
+  // chain fit and outward extension, one row per iteration; while a row is
+  // stepped, the chain hits' coordinates are loaded two rows ahead (their
+  // indices three) and the next row's grid word one row ahead
   const int32_t hk1 = r0 + 1 <= rl ? H[(size_t)(r0 + 1) * T] : -1;
   float2 hnx = hk1 >= 0 ? d.syz[hk1] : make_float2(0.0f, 0.0f);
   int32_t hk2 = r0 + 2 <= rl ? H[(size_t)(r0 + 2) * T] : -1;
+  float2 hn2 = hk2 >= 0 ? d.syz[hk2] : make_float2(0.0f, 0.0f);
+  int32_t hk3 = r0 + 3 <= rl ? H[(size_t)(r0 + 3) * T] : -1;
   uint2 mnx = r0 + 1 < R && r0 + 1 > rl ? d.row_meta[srb + r0 + 1] : make_uint2(0u, 0u);
   for (uint32_t r = r0 + 1; r < R; ++r) {
     // issue priority by the rows still ahead (outward, then about as many inward): a wave far from its
@@ -635,8 +637,9 @@ __device__ __forceinline__ bool up_one(const DevPtrs& d, const KfConst& k, const
     const bool chain = r <= rl;
     const float2 hc = hnx;
     const uint2 meta = mnx;
-    hnx = hk2 >= 0 ? d.syz[hk2] : make_float2(0.0f, 0.0f);
-    hk2 = r + 2 <= rl ? H[(size_t)(r + 2) * T] : -1;
+    hnx = hn2;
+    hn2 = hk3 >= 0 ? d.syz[hk3] : make_float2(0.0f, 0.0f);
+    hk3 = r + 3 <= rl ? H[(size_t)(r + 3) * T] : -1;
     if (r + 1 < R && r + 1 > rl) mnx = d.row_meta[srb + r + 1];
     ++steps;
     const RowK rk = lrows[r];
@@ -772,11 +775,12 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     uint32_t rin = rout;
     float xprev = lrows[rout].x;
     int miss = 0;
-    // the outward pass's hit of the next row and its coordinates are loaded one
-    // and two rows ahead, the next row's grid word one row ahead
+    // the outward pass's row -> hit entries are loaded three rows ahead and
+    // their coordinates two rows ahead, the next row's grid word one row ahead
     auto known = [&](int r) { return r >= (int)r0 && r >= 0 ? H[(size_t)r * T] : -1; };
-    int32_t hA = known((int)rout - 1), hB = known((int)rout - 2);
+    int32_t hA = known((int)rout - 1), hB = known((int)rout - 2), hC = known((int)rout - 3);
     float2 vA = hA >= 0 ? d.syz[hA] : make_float2(0.0f, 0.0f);
+    float2 vB = hB >= 0 ? d.syz[hB] : make_float2(0.0f, 0.0f);
     uint2 mA = rout >= 1 ? d.row_meta[srb + rout - 1] : make_uint2(0u, 0u);
     for (int r = (int)rout - 1; r >= 0; --r) {
       set_priority(2 * (uint32_t)__builtin_amdgcn_readfirstlane(r), prio);
@@ -784,8 +788,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
       const float2 vk = vA;
       const uint2 meta = mA;
       hA = hB;
-      vA = hB >= 0 ? d.syz[hB] : make_float2(0.0f, 0.0f);
-      hB = known(r - 2);
+      vA = vB;
+      hB = hC;
+      vB = hC >= 0 ? d.syz[hC] : make_float2(0.0f, 0.0f);
+      hC = known(r - 3);
       if (r >= 1) mA = d.row_meta[srb + (uint32_t)r - 1];
       const RowK rk = lrows[r];
       ++steps;
