@@ -13,7 +13,12 @@
 // All work is one lane per track or per cluster, bound by HBM traffic: about
 // 40 B per track (6 coefficients, x_ref, offset) and 13 B per track cluster
 // (id, row, codes, raw pair) for the encoding, the same order for the
-// decoding; the clusters on no track cost a flag and 9 B each.
+// decoding; the clusters on no track cost a flag and 9 B each.  The decoder
+// does not search per cluster: a wave takes kChunk * 64 consecutive track
+// clusters, and each lane finds its track once and then walks forward with
+// its clusters.  (The encoder searches its track and row per cluster: both
+// searches run over small arrays that stay in cache, which measured faster
+// than chunks of clusters per lane or a per-cluster row word.)
 #include <algorithm>
 
 #include "device_common.h"
@@ -23,6 +28,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int16_t kEscape = -32768;
+constexpr uint32_t kChunk = 16;   // track clusters per decoding lane between two track searches
 
 __device__ __forceinline__ uint32_t grid_stride() { return gridDim.x * blockDim.x; }
 __device__ __forceinline__ uint32_t gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
@@ -36,6 +42,14 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint3
     else hi = mid;
   }
   return lo;
+}
+
+// Track of cluster position j, from a track t0 at or before it (first[t0] <= j),
+// never past the last track.
+__device__ __forceinline__ uint32_t walk_track(const uint32_t* first, uint32_t n_tracks, uint32_t t0, uint64_t j) {
+  uint32_t t = t0;
+  while (t + 1 < n_tracks && first[t + 1] <= j) ++t;
+  return t;
 }
 
 // c0 + u * (c1 + u * c2), u = xr - x_ref, float32, no fused multiply-add.
@@ -150,28 +164,38 @@ __global__ void __launch_bounds__(kThreads) k_codec_row_emit(CodecArgs a) {
 
 __global__ void __launch_bounds__(kThreads) k_codec_decode(DecodeArgs a) {
 #pragma clang fp contract(off)
-  for (uint64_t j = gtid(); j < a.n_cl; j += grid_stride()) {
-    const short2 k = reinterpret_cast<const short2*>(a.code)[j];
-    const uint8_t r = a.row[j];
-    float y, z;
-    if (k.x == kEscape) {
-      const float2 raw = reinterpret_cast<const float2*>(a.raw)[j];
-      y = raw.x;
-      z = raw.y;
-    } else {
-      const uint32_t t = last_le(a.first, a.n_tracks, (uint32_t)j);
-      const float* c = a.coef + 6 * (size_t)t;
-      const float xr = a.rows[r].x, xref = a.x_ref[t];
-      const float py = predict(xr, xref, c[0], c[1], c[2]);
-      const float pz = predict(xr, xref, c[3], c[4], c[5]);
-      const float dy = (float)k.x * a.q_y;
-      const float dz = (float)k.y * a.q_z;
-      y = py + dy;
-      z = pz + dz;
+  const uint64_t span = (uint64_t)kWave * kChunk;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t wave = gtid() / kWave, waves = grid_stride() / kWave;
+  for (uint64_t base = wave * span; base < a.n_cl; base += waves * span) {   // wave-uniform bounds
+    uint32_t t = 0;
+    bool found = false;
+    for (uint32_t k = 0; k < kChunk; ++k) {
+      const uint64_t j = base + lane + (uint64_t)k * kWave;
+      if (j >= a.n_cl) break;
+      const short2 c2 = reinterpret_cast<const short2*>(a.code)[j];
+      const uint8_t r = a.row[j];
+      float y, z;
+      if (c2.x == kEscape) {
+        const float2 raw = reinterpret_cast<const float2*>(a.raw)[j];
+        y = raw.x;
+        z = raw.y;
+      } else {
+        t = found ? walk_track(a.first, a.n_tracks, t, j) : last_le(a.first, a.n_tracks, (uint32_t)j);
+        found = true;
+        const float* c = a.coef + 6 * (size_t)t;
+        const float xr = a.rows[r].x, xref = a.x_ref[t];
+        const float py = predict(xr, xref, c[0], c[1], c[2]);
+        const float pz = predict(xr, xref, c[3], c[4], c[5]);
+        const float dy = (float)c2.x * a.q_y;
+        const float dz = (float)c2.y * a.q_z;
+        y = py + dy;
+        z = pz + dz;
+      }
+      a.y_out[j] = y;
+      a.z_out[j] = z;
+      a.row_out[j] = r;
     }
-    a.y_out[j] = y;
-    a.z_out[j] = z;
-    a.row_out[j] = r;
   }
   for (uint64_t k = gtid(); k < a.n_un; k += grid_stride()) {
     const float2 v = reinterpret_cast<const float2*>(a.un_yz)[k];
@@ -199,7 +223,8 @@ void launch_codec_encode(const CodecArgs& a, unsigned long long* scan_blocks, hi
 }
 
 void launch_codec_decode(const DecodeArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_codec_decode, dim3(blocks_for(std::max<uint64_t>(a.n_cl, a.n_un))), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_codec_decode, dim3(blocks_for(std::max<uint64_t>((a.n_cl + kChunk - 1) / kChunk, a.n_un))),
+                     dim3(kThreads), 0, s, a);
 }
 
 }  // namespace tpc
