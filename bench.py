@@ -454,16 +454,16 @@ def main():
         for k, v in passes.items():
             bd_acc.setdefault(k, []).append(v)
     tr.set_timing(False)
-    # end to end with the track arrays copied to pinned host memory
+    # end to end with the track arrays copied to pinned host memory (read there as numpy views)
     n_e2e = max(3, args.steps // 2)
     t1 = time.perf_counter()
     for _ in range(n_e2e):
         if args.mode == "batched":
-            out = tr.track(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+            n_out = tr.track_to_host(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi, lambda t: t.n_tracks)
         else:
-            out = batching.track_per_sector(tr, y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi)
+            n_out = batching.track_per_sector(tr, y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi).n_tracks
     e2e = time.perf_counter() - t1
-    assert out.n_tracks == counts["n_tracks"]
+    assert n_out == counts["n_tracks"]
 
     value = N * args.steps / elapsed
     pass_ms = {k: float(np.mean(v)) for k, v in bd_acc.items()}

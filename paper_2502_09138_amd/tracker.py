@@ -302,7 +302,10 @@ class Tracker:
         self._n_clusters = {rid.value: int(f.n_clusters)}
         return rid.value
 
-    def get(self, rid, blocking=True):
+    def get(self, rid, blocking=True, copy=True):
+        """The tracks of request rid, copied to the tracker's pinned host buffers by the library.
+        copy=True returns numpy arrays of their own; copy=False returns views of the pinned buffers,
+        valid until release(rid) (the next request overwrites them)."""
         t = _Tracks()
         st = load().tpc_get_tracks(self._h, rid, 1 if blocking else 0, C.byref(t))
         if st == TPC_E_NOTREADY:
@@ -313,7 +316,7 @@ class Tracker:
         def arr(ptr, count, dt):
             if count == 0:
                 return np.zeros(0, dt)
-            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=True)
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=copy)
 
         return Tracks(n_tracklets=t.n_tracklets, error_flags=t.error_flags,
                       sector=arr(t.track_sector, n, np.uint32), start=arr(t.track_start, n, np.uint32),
@@ -422,6 +425,15 @@ class Tracker:
         rid = self.submit(y, z, row_offsets, z_lo, z_hi, host=host, scratch=scratch)
         try:
             return self.get(rid)
+        finally:
+            self.release(rid)
+
+    def track_to_host(self, y, z, row_offsets, z_lo, z_hi, consume):
+        """Tracks one frame and calls consume(tracks) on views of the pinned host copy of its outputs
+        (no further copy), before the request is released; returns what consume returns."""
+        rid = self.submit(y, z, row_offsets, z_lo, z_hi)
+        try:
+            return consume(self.get(rid, copy=False))
         finally:
             self.release(rid)
 

@@ -128,6 +128,21 @@ def test_determinism_and_host_input(torch_cuda):
             assert np.array_equal(getattr(a, f), getattr(x, f)), f
 
 
+def test_host_views_match_copies(torch_cuda):
+    """Tracks read as views of the pinned host copy (before release) equal the copied arrays."""
+    ev = synth.single_sector(seed=4)
+    tr = _tracker(ev)
+    a = tr.track_event(ev)
+    y = torch_cuda.from_numpy(ev.y).to("cuda:0")
+    z = torch_cuda.from_numpy(ev.z).to("cuda:0")
+    fields = ("sector", "start", "first", "cluster_ids", "x_ref", "param", "cov", "chi2", "ndf")
+    views = tr.track_to_host(y, z, ev.row_offsets, ev.sector_z_lo, ev.sector_z_hi,
+                             lambda t: {f: np.array(getattr(t, f), copy=True) for f in fields})
+    assert a.n_tracks > 10
+    for f in fields:
+        assert np.array_equal(getattr(a, f), views[f]), f
+
+
 def test_pass_timing_mask(torch_cuda):
     """Timing selects passes; untimed passes are absent and results do not depend on it."""
     from paper_2502_09138_amd.tracker import PASS_NAMES, TrackerError
