@@ -235,7 +235,8 @@ class Server:
                 tr = self.trackers[s]
                 status, out = 0, None
                 try:
-                    out = tr.get(rid, blocking=False)
+                    # in pinned host memory now; copied out of it only where the outputs are kept
+                    out = tr.get(rid, blocking=False, copy=keep_outputs)
                     if out is None:
                         continue
                 except TrackerError as e:
