@@ -21,7 +21,14 @@ namespace {
 
 constexpr int kThreads = 64;             // one wave; one hit per lane
 constexpr uint32_t kSliceHits = 256;     // staged hits per adjacent row
-constexpr uint32_t kSliceBins = 256;     // staged bin starts per adjacent row
+// Staged bin starts per adjacent row.  The 4-slot kernel stages 128 (5 KB of
+// LDS per wave) and is held to 72 VGPRs, which lets seven waves share a SIMD
+// instead of six (-6% on the 32-orbit frame); the 8-slot kernel would spill
+// at that size and keeps 256.
+template <int kUpSlots>
+constexpr uint32_t slice_bins() { return kUpSlots == 4 ? 128u : 256u; }
+template <int kUpSlots>
+constexpr int link_waves() { return kUpSlots == 4 ? 7 : 5; }
 
 struct RowView {
   const float2* yz;        // indexed by position - off
@@ -141,6 +148,7 @@ __device__ __forceinline__ float wave_maxf(float v) {
 
 // View of adjacent row sr restricted to the z-lines reachable from z in
 // [zmin, zmax] with window half-width wz; staged into (lyz, lbs) when it fits.
+template <uint32_t kBins>
 __device__ __forceinline__ RowView adjacent_view(const DevPtrs& d, uint32_t sr, float zmin, float zmax, float wz,
                                                  bool stage, float2* lyz, uint32_t* lbs) {
 #pragma clang fp contract(off)
@@ -160,7 +168,7 @@ __device__ __forceinline__ RowView adjacent_view(const DevPtrs& d, uint32_t sr, 
   const int iz0 = bin1(zmin - pz, v.z_lo, v.inv_wz, v.nz), iz1 = bin1(zmax + pz, v.z_lo, v.inv_wz, v.nz);
   const uint32_t b0 = (uint32_t)(iz0 * v.ny), b1 = (uint32_t)((iz1 + 1) * v.ny);   // bins [b0, b1), starts [b0, b1]
   const uint32_t s0 = bs[b0], s1 = bs[b1];
-  if (stage && s1 - s0 <= kSliceHits && b1 - b0 + 1 <= kSliceBins) {
+  if (stage && s1 - s0 <= kSliceHits && b1 - b0 + 1 <= kBins) {
     for (uint32_t j = threadIdx.x; j < s1 - s0; j += kThreads) lyz[j] = d.syz[s0 + j];
     for (uint32_t j = threadIdx.x; j <= b1 - b0; j += kThreads) lbs[j] = bs[b0 + j];
     v.yz = lyz;
@@ -177,9 +185,10 @@ __device__ __forceinline__ RowView adjacent_view(const DevPtrs& d, uint32_t sr, 
 }
 
 template <int kUpSlots>
-__global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho, uint32_t G) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(link_waves<kUpSlots>())))
+k_links(DevPtrs d, float rho, uint32_t G) {
   __shared__ float2 lyz[2][kSliceHits];
-  __shared__ uint32_t lbs[2][kSliceBins];
+  __shared__ uint32_t lbs[2][slice_bins<kUpSlots>()];
   // Tiles go to the XCDs (block b runs on XCD b % kXcds) in groups of G
   // consecutive tiles, group g on XCD g % kXcds: the adjacent-row runs that
   // tiles of rows r - 1 and r + 1 both stage are then read through one L2
@@ -206,8 +215,8 @@ __global__ void __launch_bounds__(kThreads) k_links(DevPtrs d, float rho, uint32
   // order: such a tile searches the whole adjacent rows in global memory
   const bool stage = !__any(mine && !(fabsf(h.y) <= kMaxCoord));
   const RowConst rc = d.rows[row];
-  const RowView dn = adjacent_view(d, sr - 1, zmin, zmax, rc.wz_dn, stage, lyz[0], lbs[0]);
-  const RowView up = adjacent_view(d, sr + 1, zmin, zmax, rc.wz_up, stage, lyz[1], lbs[1]);
+  const RowView dn = adjacent_view<slice_bins<kUpSlots>()>(d, sr - 1, zmin, zmax, rc.wz_dn, stage, lyz[0], lbs[0]);
+  const RowView up = adjacent_view<slice_bins<kUpSlots>()>(d, sr + 1, zmin, zmax, rc.wz_up, stage, lyz[1], lbs[1]);
   __syncthreads();
   if (mine) link_hit<kUpSlots>(d, p, h, dn, up, rc, rho);
 }
