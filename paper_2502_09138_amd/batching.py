@@ -86,9 +86,10 @@ def shape_class(row_offsets, n_rows=N_ROWS):
     return (b(S), b(mx), b(mean))
 
 
-# Values of each tuning knob (Tracker.set_knobs), the automatic setting first.
+# Values of each tuning knob (Tracker.set_knobs), the one the tuner starts from first: the automatic
+# setting, except for the K2 grouping, which starts from the grouping with the least HBM traffic.
 KNOB_SPACE = {"schedule": (1, 2), "select_tile_rows": (0, 2, 4, -1), "refit_order": (0, 1), "link_slots": (8, 4),
-              "link_group": (64, 1, 512, -1)}
+              "link_group": (-1, 64, 1, 512)}
 
 
 def knob_grid(space=None):
@@ -111,14 +112,17 @@ class ScheduleTuner:
     caches the choice, optionally in a JSON file.  With ``candidates`` (knob dicts or plain schedule
     numbers) every candidate is timed; without, the knobs of ``space`` are tuned one at a time, each over
     its values with the others at their best so far (every setting timed once at most).  A setting's
-    time is the sum of all passes (HIP events), best of ``repeats``."""
+    time is the sum of all passes (HIP events), best of ``repeats``; a setting replaces the one chosen
+    so far (the earlier candidate, or the knob's first value) only if it is faster by more than the
+    fraction ``tie``, so run-to-run noise does not decide between equals."""
 
-    def __init__(self, tracker, candidates=None, repeats=2, cache_path=None, arch=None, space=None):
+    def __init__(self, tracker, candidates=None, repeats=2, cache_path=None, arch=None, space=None, tie=0.005):
         self.tracker = tracker
         self.candidates = None if candidates is None else \
             tuple(c if isinstance(c, dict) else {"schedule": int(c)} for c in candidates)
         self.space = dict(KNOB_SPACE if space is None else space)
         self.repeats = repeats
+        self.tie = tie
         self.cache_path = cache_path
         self.arch = arch or "gfx950"
         self.cache = {}
@@ -146,6 +150,15 @@ class ScheduleTuner:
             self.timings[(key, tag)] = ms
         return self.timings[(key, tag)]
 
+    def _pick(self, key, settings, frame):
+        """The first setting, replaced by any later one faster by more than the tie fraction."""
+        best, t_best = None, None
+        for c in settings:
+            t = self._time(key, c, frame)
+            if best is None or t < t_best * (1.0 - self.tie):
+                best, t_best = c, t
+        return best
+
     def choose(self, y, z, row_offsets, z_lo, z_hi):
         """The best knob setting for this frame's shape class (applied to the tracker); with plain
         schedule candidates, the schedule number."""
@@ -155,11 +168,11 @@ class ScheduleTuner:
             tr = self.tracker
             tr.set_timing(True)
             if self.candidates is not None:
-                best = min(self.candidates, key=lambda c: self._time(key, c, frame))
+                best = self._pick(key, self.candidates, frame)
             else:
                 best = {k: v[0] for k, v in self.space.items()}
                 for name, values in self.space.items():
-                    best = min((dict(best, **{name: v}) for v in values), key=lambda c: self._time(key, c, frame))
+                    best = self._pick(key, [dict(best, **{name: v}) for v in values], frame)
             tr.set_timing(False)
             self.cache[key] = best
             if self.cache_path:

@@ -75,6 +75,45 @@ def test_per_sector_requests_match_the_batched_frame():
 
 
 @pytest.mark.gpu
+class _TimedTracker:
+    """Stands in for a Tracker in the tuner: each knob setting has a fixed total pass time."""
+
+    def __init__(self, ms_of):
+        self.ms_of, self.knobs = ms_of, {}
+
+    def set_timing(self, on):
+        pass
+
+    def set_knobs(self, **knobs):
+        self.knobs = dict(knobs)
+
+    def submit(self, *frame):
+        return 1
+
+    def get_device(self, rid):
+        return {}
+
+    def release(self, rid):
+        pass
+
+    def pass_times(self):
+        return {"tracklets": self.ms_of(self.knobs)}
+
+
+def test_tuner_keeps_the_incumbent_within_the_tie_fraction():
+    """A knob value replaces the one chosen so far only if faster by more than the tie fraction."""
+    space = {"a": (0, 1, 2), "b": (0, 1)}
+    times = {(0, 0): 10.0, (1, 0): 9.98, (2, 0): 9.0, (2, 1): 8.99}
+    tr = _TimedTracker(lambda k: times.get((k["a"], k["b"]), 20.0))
+    ro = np.zeros(R + 1, np.uint32)
+    c = batching.ScheduleTuner(tr, space=space, repeats=1, tie=0.005).choose(None, None, ro, None, None)
+    assert c == {"a": 2, "b": 0}            # 9.98 ties with 10.0; 9.0 wins; 8.99 ties with 9.0
+    c = batching.ScheduleTuner(tr, space=space, repeats=1, tie=0.0).choose(None, None, ro, None, None)
+    assert c == {"a": 2, "b": 1}            # without the tie rule the strict minimum wins
+    cands = ({"a": 0, "b": 0}, {"a": 1, "b": 0})
+    assert batching.ScheduleTuner(tr, candidates=cands, repeats=1).choose(None, None, ro, None, None) == cands[0]
+
+
 def test_schedule_tuner_caches_per_shape_class(tmp_path):
     import torch
     if not torch.cuda.is_available():
