@@ -74,7 +74,6 @@ def test_per_sector_requests_match_the_batched_frame():
         tr.close()
 
 
-@pytest.mark.gpu
 class _TimedTracker:
     """Stands in for a Tracker in the tuner: each knob setting has a fixed total pass time."""
 
@@ -114,6 +113,7 @@ def test_tuner_keeps_the_incumbent_within_the_tie_fraction():
     assert batching.ScheduleTuner(tr, candidates=cands, repeats=1).choose(None, None, ro, None, None) == cands[0]
 
 
+@pytest.mark.gpu
 def test_schedule_tuner_caches_per_shape_class(tmp_path):
     import torch
     if not torch.cuda.is_available():
