@@ -23,14 +23,14 @@ constexpr int kThreads = 64;             // one wave; one hit per lane
 constexpr uint32_t kSliceHits = 256;     // staged hits per adjacent row
 // Staged bin starts per adjacent row, and waves per SIMD.  The 4-slot kernel
 // stages 128 (5 KB of LDS per wave) and is held to 72 VGPRs, which lets seven
-// waves share a SIMD instead of six (-7% on the 32-orbit frame); the 8-slot
-// kernel keeps 256 and is held to 80 VGPRs for six waves instead of five
-// (-4% on the uneven chunks; at seven waves it spills inside its loops and
-// runs twice as long).
+// waves share a SIMD instead of six (-7% on the 32-orbit frame).  The 8-slot
+// kernel keeps 256 and its 89 VGPRs (five waves): held to 80 for six waves it
+// spills, 4% faster on the uneven chunks but its spill stores triple its HBM
+// traffic; at seven waves it runs twice as long.
 template <int kUpSlots>
 constexpr uint32_t slice_bins() { return kUpSlots == 4 ? 128u : 256u; }
 template <int kUpSlots>
-constexpr int link_waves() { return kUpSlots == 4 ? 7 : 6; }
+constexpr int link_waves() { return kUpSlots == 4 ? 7 : 5; }
 
 struct RowView {
   const float2* yz;        // indexed by position - off
