@@ -52,11 +52,12 @@ PROFILES = {
     "time_frame": {
         "digests": ("e6f5144456141a8ece92fb362dab16b7baf29c14", "c842c467a72239a1275ba70e0d941297d2d258a8",
                     "0c2bdc7fab0f213bed5c4784cc480462ad908377", "b4b103e57db5db269528a9bdae40217f2bb52ff1",
-                    "b3ba03b8d0b88dea4798aff54380ee4fa0a1121f"),
-        "knobs": {"schedule": 1, "select_tile_rows": 4, "refit_order": 0, "link_slots": 4, "link_group": 512},
+                    "9cd7cf284155efdc8f0dcaf15d9b2a7a4972b985"),
+        "knobs": {"schedule": 1, "select_tile_rows": 4, "refit_order": 0, "link_slots": 4, "link_group": -1,
+                  "select_threads": 1024},
         # tracklets: k_seed + k_up + k_sort + k_down + k_guard; VALU of k_up and k_down (the rest is < 5%)
-        "traffic_bytes": {"tracklets": 5_465_370_000, "grid": 292_360_000, "neighbours": 193_240_000},
-        "valu_insts": {"tracklets": 960_464_343, "grid": 21_682_775, "neighbours": 247_356_471},
+        "traffic_bytes": {"tracklets": 5_473_990_000, "grid": 292_040_000, "neighbours": 182_370_000},
+        "valu_insts": {"tracklets": 960_531_614, "grid": 21_682_775, "neighbours": 247_349_791},
         "files": "profiles/time_frame_hbm_traffic.md, profiles/time_frame_sq_counters.md",
     },
 }

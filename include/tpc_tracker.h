@@ -445,13 +445,16 @@ tpc_status tpc_set_tracklet_schedule(tpc_tracker* t, int32_t schedule);
  *                               (64 hits each) given to one XCD before the
  *                               next XCD's group (1 deals them out one by
  *                               one); -1: one contiguous eighth per XCD
+ *   TPC_KNOB_SELECT_THREADS     0 auto (512), 256, 512 or 1024: workgroup size
+ *                               of the C6 selector's tile kernels
  * TPC_E_INVAL for an unknown knob or value, or while a request is in flight. */
 enum {
   TPC_KNOB_TRACKLET_SCHEDULE = 1,
   TPC_KNOB_SELECT_TILE_ROWS = 2,
   TPC_KNOB_REFIT_ORDER = 3,
   TPC_KNOB_LINK_SLOTS = 4,
-  TPC_KNOB_LINK_GROUP = 5
+  TPC_KNOB_LINK_GROUP = 5,
+  TPC_KNOB_SELECT_THREADS = 6
 };
 tpc_status tpc_set_knob(tpc_tracker* t, int32_t knob, int32_t value);
 

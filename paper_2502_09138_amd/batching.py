@@ -89,7 +89,7 @@ def shape_class(row_offsets, n_rows=N_ROWS):
 # Values of each tuning knob (Tracker.set_knobs), the one the tuner starts from first: the automatic
 # setting, except for the K2 grouping, which starts from the grouping with the least HBM traffic.
 KNOB_SPACE = {"schedule": (1, 2), "select_tile_rows": (0, 2, 4, -1), "refit_order": (0, 1), "link_slots": (8, 4),
-              "link_group": (-1, 64, 1, 512)}
+              "link_group": (-1, 64, 1, 512), "select_threads": (512, 256, 1024)}
 
 
 def knob_grid(space=None):

@@ -79,13 +79,14 @@ struct TileHits {
   uint32_t key[kBatch];
 };
 
+template <int kT>
 __device__ __forceinline__ void tile_hits(const DevPtrs& d, const KfConst& k, const Tile& tl, uint32_t i0,
                                           TileHits& th) {
   const uint32_t T = d.tcap;
   int32_t nh[kBatch], rin[kBatch], rout[kBatch];
 #pragma unroll
   for (int u = 0; u < kBatch; ++u) {
-    const uint32_t i = i0 + u * kThreads;
+    const uint32_t i = i0 + u * kT;
     const bool in = i < tl.te;
     nh[u] = in ? d.tk_info[i] : 0;
     rin[u] = in ? d.tk_info[T + i] : 0;
@@ -93,7 +94,7 @@ __device__ __forceinline__ void tile_hits(const DevPtrs& d, const KfConst& k, co
   }
 #pragma unroll
   for (int u = 0; u < kBatch; ++u) {
-    const uint32_t i = i0 + u * kThreads;
+    const uint32_t i = i0 + u * kT;
     const bool ok = i < tl.te && nh[u] >= k.min_tracklet_hits;
     const int32_t lo = max((int32_t)tl.ra, rin[u]), hi = min((int32_t)tl.rb - 1, rout[u]);
     th.key[u] = key32((uint32_t)nh[u], i);
@@ -105,7 +106,8 @@ __device__ __forceinline__ void tile_hits(const DevPtrs& d, const KfConst& k, co
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_claim_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
+template <int kT>
+__global__ void __launch_bounds__(kT) k_claim_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
   extern __shared__ uint32_t wt[];
   const uint32_t v = tile_index(d, n_tiles);
   if (v >= d.S * n_tiles) return;
@@ -113,9 +115,9 @@ __global__ void __launch_bounds__(kThreads) k_claim_tiles(DevPtrs d, KfConst k, 
   const uint32_t T = d.tcap;
   for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) wt[j] = 0u;
   __syncthreads();
-  for (uint32_t i0 = tl.ts + threadIdx.x; i0 < tl.te; i0 += kBatch * kThreads) {
+  for (uint32_t i0 = tl.ts + threadIdx.x; i0 < tl.te; i0 += kBatch * kT) {
     TileHits th;
-    tile_hits(d, k, tl, i0, th);
+    tile_hits<kT>(d, k, tl, i0, th);
 #pragma unroll
     for (int u = 0; u < kBatch; ++u)
 #pragma unroll
@@ -126,12 +128,12 @@ __global__ void __launch_bounds__(kThreads) k_claim_tiles(DevPtrs d, KfConst k, 
   for (uint32_t j = threadIdx.x; j < tl.n; j += blockDim.x) d.W[tl.first + j] = wt[j];
   // every claim on the tile's rows is in: count each tracklet's owned hits here
   const uint32_t tt = v % n_tiles;
-  for (uint32_t i0 = tl.ts + threadIdx.x; i0 < tl.te; i0 += kBatch * kThreads) {
+  for (uint32_t i0 = tl.ts + threadIdx.x; i0 < tl.te; i0 += kBatch * kT) {
     TileHits th;
-    tile_hits(d, k, tl, i0, th);
+    tile_hits<kT>(d, k, tl, i0, th);
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const uint32_t i = i0 + u * kThreads;
+      const uint32_t i = i0 + u * kT;
       uint32_t cnt = 0;
 #pragma unroll
       for (int rr = 0; rr < kTileRowsMax; ++rr)
@@ -174,7 +176,8 @@ __global__ void __launch_bounds__(kThreads) k_accept(DevPtrs d, KfConst k, uint3
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_emit_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
+template <int kT>
+__global__ void __launch_bounds__(kT) k_emit_tiles(DevPtrs d, KfConst k, uint32_t tile_rows, uint32_t n_tiles) {
   extern __shared__ uint32_t wt[];
   const uint32_t v = tile_index(d, n_tiles);
   if (v >= d.S * n_tiles) return;
@@ -186,16 +189,16 @@ __global__ void __launch_bounds__(kThreads) k_emit_tiles(DevPtrs d, KfConst k, u
   const uint32_t v1 = min((uint32_t)(d.tk_scan[tl.te] & 0xFFFFFFFFull), d.max_tracks);
   __syncthreads();
   // kBatch tracks per thread at a time, each stage's loads issued together
-  for (uint32_t vb = v0 + threadIdx.x; vb < v1; vb += kBatch * kThreads) {
+  for (uint32_t vb = v0 + threadIdx.x; vb < v1; vb += kBatch * kT) {
     uint32_t i[kBatch];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) i[u] = vb + u * kThreads < v1 ? d.acc_list[vb + u * kThreads] : 0u;
+    for (int u = 0; u < kBatch; ++u) i[u] = vb + u * kT < v1 ? d.acc_list[vb + u * kT] : 0u;
     bool go[kBatch];
     uint32_t o[kBatch], key[kBatch];
     int32_t lo[kBatch], hi[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const bool in = vb + u * kThreads < v1;
+      const bool in = vb + u * kT < v1;
       const unsigned long long pk = in ? d.tk_pack[i[u]] : 0ull;
       const unsigned long long co = in ? d.tk_scan[i[u]] >> 32 : 0ull;
       const int32_t nh = in ? d.tk_info[i[u]] : 0;
@@ -358,11 +361,18 @@ void launch_select(const DevPtrs& d, const KfConst& k, uint32_t tile_rows, hipSt
     const size_t lds = (size_t)d.tile_cap * sizeof(uint32_t);
     const uint32_t G = (n_tiles + 1) / 2, groups = (d.S * n_tiles + G - 1) / G;
     const dim3 tiles((groups + kXcds - 1) / kXcds * kXcds * G);   // every group slot of every XCD
-    hipLaunchKernelGGL(k_claim_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
+    // workgroup size of the tile kernels: their LDS holds the tile's ownership words (up to 48 KB),
+    // which bounds the workgroups per CU, so larger workgroups put more waves on each tile
+    const uint32_t nt = d.k6_threads == 1024 ? 1024u : d.k6_threads == 256 ? 256u : 512u;
+    if (nt == 1024) hipLaunchKernelGGL(k_claim_tiles<1024>, tiles, dim3(nt), lds, s, d, k, tile_rows, n_tiles);
+    else if (nt == 256) hipLaunchKernelGGL(k_claim_tiles<256>, tiles, dim3(nt), lds, s, d, k, tile_rows, n_tiles);
+    else hipLaunchKernelGGL(k_claim_tiles<512>, tiles, dim3(nt), lds, s, d, k, tile_rows, n_tiles);
     hipLaunchKernelGGL(k_accept, dim3(blocks), dim3(kThreads), 0, s, d, k, tile_rows);
     launch_scan_u64(d.tk_pack, d.tk_scan, &d.hdr->n_starts, d.tcap, d.scan_blocks, s);
     hipLaunchKernelGGL(k_records, dim3(blocks), dim3(kThreads), 0, s, d, k);
-    hipLaunchKernelGGL(k_emit_tiles, tiles, dim3(kThreads), lds, s, d, k, tile_rows, n_tiles);
+    if (nt == 1024) hipLaunchKernelGGL(k_emit_tiles<1024>, tiles, dim3(nt), lds, s, d, k, tile_rows, n_tiles);
+    else if (nt == 256) hipLaunchKernelGGL(k_emit_tiles<256>, tiles, dim3(nt), lds, s, d, k, tile_rows, n_tiles);
+    else hipLaunchKernelGGL(k_emit_tiles<512>, tiles, dim3(nt), lds, s, d, k, tile_rows, n_tiles);
   } else {
     hipLaunchKernelGGL(k_clear_w, dim3(xcd_grid(std::min<uint32_t>(8192, std::max<uint32_t>(1, (d.N + kThreads - 1) / kThreads)))),
                        dim3(kThreads), 0, s, d);

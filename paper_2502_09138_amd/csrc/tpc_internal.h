@@ -120,6 +120,7 @@ struct DevPtrs {
   int32_t k5_refit_order;    // 0 (sector, outermost row) buckets, 1 tracklet order
   int32_t k2_slots;          // K2 up-candidate slots per lane: 4 or 8 (0 = 8)
   uint32_t k2_group;         // K2 tiles per XCD group (1: round robin, kLinkGroupEighth: an eighth of the tiles)
+  uint32_t k6_threads;       // workgroup size of the K6 tile kernels: 256, 512 or 1024
   uint32_t S, R, SR, N;
   uint32_t tcap;
   uint32_t tile_cap;         // LDS words of one selector tile (max hits in a sector's row block)

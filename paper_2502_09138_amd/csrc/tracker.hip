@@ -48,6 +48,7 @@ constexpr uint64_t kScratchBytes = TPC_SCRATCH_BYTES;
 constexpr int kMaxDevices = 64;
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kSelectTileWords = 12288;     // 48 KB of LDS per selector tile at most
+constexpr uint32_t kSelectThreadsAuto = 512;    // TPC_KNOB_SELECT_THREADS = 0: K6 tile workgroup size
 constexpr uint32_t kLinkGroupAuto = 64;          // TPC_KNOB_LINK_GROUP = 0: K2 tiles per XCD group
 constexpr uint32_t kSelectGlobal = 0xFFFFFFFFu;  // TPC_KNOB_SELECT_TILE_ROWS = -1: the global-memory selector
 
@@ -313,6 +314,7 @@ void carve(tpc_tracker* t) {
   d.grid_k = cfg->grid_hits_per_bin;
   d.k5_mode = cfg->tracklet_schedule;
   d.k2_group = kLinkGroupAuto;
+  d.k6_threads = kSelectThreadsAuto;
   d.rho = k.rho;
   d.R = R;
   d.tcap = (uint32_t)caps.T;
@@ -1112,6 +1114,11 @@ tpc_status tpc_set_knob(tpc_tracker* t, int32_t knob, int32_t value) {
     case TPC_KNOB_LINK_SLOTS:
       if (value != 0 && value != 4 && value != 8) return fail(TPC_E_INVAL, "link slots must be 0, 4 or 8");
       t->d.k2_slots = value;
+      return TPC_OK;
+    case TPC_KNOB_SELECT_THREADS:
+      if (value != 0 && value != 256 && value != 512 && value != 1024)
+        return fail(TPC_E_INVAL, "select threads must be 0, 256, 512 or 1024");
+      t->d.k6_threads = value == 0 ? kSelectThreadsAuto : (uint32_t)value;
       return TPC_OK;
     case TPC_KNOB_LINK_GROUP:
       if (value < -1 || value > 4096) return fail(TPC_E_INVAL, "link group must be 0 (auto), -1 or 1..4096 tiles");

@@ -101,7 +101,8 @@ class _CodecCounts(C.Structure):
 
 TPC_CODEC_ESCAPE = -32768
 # tuning knobs (tpc_set_knob)
-KNOBS = {"schedule": 1, "select_tile_rows": 2, "refit_order": 3, "link_slots": 4, "link_group": 5}
+KNOBS = {"schedule": 1, "select_tile_rows": 2, "refit_order": 3, "link_slots": 4, "link_group": 5,
+         "select_threads": 6}
 CODEC_FIELDS = ("coef", "x_ref", "first", "row", "code", "raw", "un_row", "un_yz")
 
 EXPORTED = ("tpc_default_config", "tpc_workspace_bytes", "tpc_tracker_create", "tpc_tracker_destroy",
@@ -471,7 +472,8 @@ class Tracker:
         """Tuning knobs for later requests (results identical under every setting): schedule (0 auto,
         1 lane-per-tracklet pipeline, 2 row-synchronous), select_tile_rows (0 auto, 1, 2, 4, -1 global),
         refit_order (0 bucket order, 1 tracklet order), link_slots (0 auto, 4, 8), link_group (0 auto,
-        1..4096 consecutive K2 tiles per XCD group, -1 an eighth of the tiles per XCD)."""
+        1..4096 consecutive K2 tiles per XCD group, -1 an eighth of the tiles per XCD), select_threads (0 auto,
+        256, 512, 1024: workgroup size of the K6 tile kernels)."""
         for name, value in knobs.items():
             if name not in KNOBS:
                 raise ValueError(f"unknown knob {name}")

@@ -143,7 +143,7 @@ def test_schedule_tuner_caches_per_shape_class(tmp_path):
 @pytest.mark.gpu
 def test_every_knob_setting_gives_identical_results():
     """The tuner's knobs change speed only: every setting of schedule x selector tile rows x refit
-    order x K2 slots x K2 XCD grouping gives bit-identical outputs (six sectors of the 32-orbit frame: rows beyond the
+    order x K2 slots x K2 XCD grouping x selector workgroup size gives bit-identical outputs (six sectors of the 32-orbit frame: rows beyond the
     row-synchronous stage; the central event's first four sectors: rows within it)."""
     import torch
     if not torch.cuda.is_available():
@@ -213,14 +213,15 @@ def test_knobs_reject_unknown_values():
     tr = Tracker(default_config(), max_clusters=1000, max_sectors=1)
     try:
         for knobs in ({"schedule": 3}, {"select_tile_rows": 3}, {"select_tile_rows": 8}, {"refit_order": 2},
-                      {"link_slots": 6}, {"link_group": -2}, {"link_group": 4097}):
+                      {"link_slots": 6}, {"link_group": -2}, {"link_group": 4097}, {"select_threads": 128},
+                      {"select_threads": 2048}):
             with pytest.raises(TrackerError) as e:
                 tr.set_knobs(**knobs)
             assert e.value.status == TPC_E_INVAL, knobs
         with pytest.raises(ValueError):
             tr.set_knobs(waves=4)
         tr.set_knobs(schedule=0, select_tile_rows=-1, refit_order=1, link_slots=4, link_group=-1)   # all accepted
-        tr.set_knobs(link_group=4096)
+        tr.set_knobs(link_group=4096, select_threads=1024)
         tr.set_knobs(link_group=0)
     finally:
         tr.close()
